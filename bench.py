@@ -1,0 +1,174 @@
+"""Benchmark: SGD steps/s and HBM GB/s of the sampled-gradient step.
+
+Workload (default): the 300 x 300 x 300 FP32 tensor, R = 10, B = 256,
+factors N(0,1) with column congruence 0.6 and 10% of rows scaled x20, noise
+at 30 dB SNR, AdaGrad with the Euclidean importance sampler (EAdawsCPD).
+One "step" is one full pass of the method's hot path (mode draw, per-mode
+CDFs, sampling, fibre gather, KRP rows, reweighted gradient, update); the
+timed region is K consecutive steps of one persistent launch, inputs already
+resident in HBM.
+
+Prints ONE JSON line (rank 0).  Extra fields: the HBM roofline of the step
+kernel, the FP64 oracle timed on a bounded sample on the host, and
+steps-to-fit / time-to-fit 0.99 for the importance and uniform samplers.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SGD steps/s + HBM GB/s (sampled gradient); solves/s & p99 time-to-fit 0.99"
+HBM_PEAK_GBPS = 8000.0
+ETA = 0.5
+
+
+def step_bytes(dims, R, B, elem):
+    """Algorithmic HBM bytes of one step, averaged over the uniform mode draw:
+    fibres B*I_n*s, gathered factor rows min(B, I_k)*R*4 for k != n, factor
+    and AdaGrad accumulator read+write 2*2*I_n*R*4, CDF rewrite 8*I_n."""
+    N = len(dims)
+    tot = 0.0
+    for n in range(N):
+        b = B * dims[n] * elem
+        b += sum(min(B, dims[k]) * R * 4 for k in range(N) if k != n)
+        b += 4 * dims[n] * R * 4
+        b += 8 * dims[n]
+        tot += b
+    return tot / N
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--sampler", default="euclidean")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fit", action="store_true", help="skip the time-to-fit runs")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, seconds):
+    """The FP64 oracle as it stands, single core, on a bounded sample of the
+    same workload (a fixed number of its steps)."""
+    import oracle as O
+    orc = O.Oracle(w["X"], w["A0"], B=w["B"], sampler="euclidean", rule="adagrad", eta=ETA,
+                   seed=w["seed"])
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        orc.step()
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 100000:
+            break
+    return {"value": n / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} steps of the same 300^3 problem ({el:.1f} s, numpy FP64, "
+                      "pure-Python Philox)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import cpd_inputs as ci
+    import paper_2103_04081_amd as P
+
+    torch.cuda.set_device(0)
+    w = ci.workload(2)
+    dims, R, B = w["dims"], w["R"], w["B"]
+    X32 = np.asfortranarray(w["X"].astype(np.float32))
+
+    def make(sampler, seed=w["seed"]):
+        return P.Decomposition(X32, w["A0"], B=B, sampler=sampler, rule="adagrad", eta=ETA,
+                               storage="f32", seed=seed)
+
+    dec = make(args.sampler)
+    stream = dec.stream
+    dec.step(args.warmup)
+    dec.sync()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    dec.step(args.steps)
+    ev1.record(stream)
+    ev1.synchronize()
+    torch.cuda.synchronize()
+    dec.sync()
+    ms = ev0.elapsed_time(ev1)
+    sec = ms / 1e3
+    steps_per_s = args.steps / sec
+    sb = step_bytes(dims, R, B, 4)
+    achieved = sb * args.steps / sec / 1e9
+    fit_after = dec.fit()
+    dec.close()
+
+    extra = {}
+    if not args.no_fit:
+        extra["time_to_fit"] = time_to_fit(make, target=0.99, every=25, max_steps=40000)
+
+    out = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "300x300x300 FP32 tensor, R=10, B=256, rho=0.6, 10% rows x20, "
+                               "SNR 30 dB; EAdawsCPD (Euclidean sampler, AdaGrad eta=0.5, b=0)",
+                   "sampler": args.sampler, "global_batch": B, "rank": R,
+                   "parallelism": "single GPU, one persistent workgroup per decomposition"},
+        "hbm_gbps": achieved,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "bytes_per_step": sb, "kernel": "chain_kernel"},
+        "fit_after_timed_steps": fit_after,
+    }
+    out.update(extra)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def time_to_fit(make, target, every, max_steps):
+    """Steps and wall time to the first fit check >= target, per sampler."""
+    import torch
+    res = {}
+    for sampler in ("euclidean", "leverage", "uniform"):
+        dec = make(sampler)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 0
+        fit = dec.fit()
+        while fit < target and steps < max_steps:
+            dec.step(every)
+            steps += every
+            fit = dec.fit()
+        el = time.perf_counter() - t0
+        res[sampler] = {"steps": steps, "seconds": el, "fit": fit, "reached": fit >= target}
+        dec.close()
+    res["check_every"] = every
+    res["target"] = target
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * cpd.h - C ABI of libcpdmi, block-randomized SGD with importance sampling
+ * for CP tensor decomposition on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Yu & Li, "A block-randomized stochastic method with importance
+ * sampling for CP tensor decomposition"): every step draws a mode n uniformly,
+ * samples B rows of the Khatri-Rao product Z^(n) by drawing one row of every
+ * other factor independently from that factor's leverage-score or
+ * squared-row-norm distribution (Section 3.1, Lemmas 2 and 4, Algorithm 3),
+ * gathers the matching mode-n fibres of the tensor (Algorithm 1), forms the
+ * sampled KRP rows H as Hadamard products of the gathered factor rows, and
+ * applies the reweighted stochastic gradient
+ *     G = A^(n) (H^T W H) - X_s^T W H,   W = diag(1 / (B p_f))
+ * (Section 3.2) with a fixed, decreasing (Theorem 9) or AdaGrad step
+ * (Algorithms 4 and 5).  Convergence is measured by fit = 1 - Tol with Tol the
+ * squared relative error of Section 5.2.
+ *
+ * Conventions
+ *   - Every call returns a cpd_status: 0 = OK, > 0 informational, < 0 error.
+ *     Nothing aborts or throws across this interface.  cpd_last_error()
+ *     returns a thread-local message for the last failing call of the thread.
+ *   - Indices are 0-based.  Mode k has size dims[k].
+ *   - The dense input tensor is stored with mode 1 varying fastest: entry
+ *     (i_0, ..., i_{N-1}) sits at offset i_0 + dims[0]*(i_1 + dims[1]*(...)),
+ *     the order in which the paper's mode-n unfolding map enumerates entries.
+ *   - Factor matrices are dims[k] x R, row-major (the R values of one row are
+ *     contiguous), FP32.
+ *   - Device pointers belong to the HIP device that is current when the call
+ *     is made; a handle remembers its device and stream.
+ *   - A handle is not thread-safe.  Distinct handles on distinct streams may
+ *     be driven concurrently from distinct threads.
+ */
+#ifndef CPD_H
+#define CPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define CPD_API __attribute__((visibility("default")))
+#else
+#define CPD_API
+#endif
+
+#define CPD_MAX_MODES 8
+#define CPD_MAX_RANK 64
+#define CPD_MAX_BATCH 4096
+#define CPD_MAX_DIM 4096
+
+typedef int32_t cpd_status;
+
+enum {
+  CPD_OK = 0,
+  CPD_PENDING = 1,              /* cpd_poll: request not finished yet */
+  CPD_E_INVALID = -1,           /* bad argument or unsupported size */
+  CPD_E_OOM = -2,               /* workspace too small / can never fit */
+  CPD_E_HIP = -3,               /* a HIP runtime call failed */
+  CPD_E_RANK_DEFICIENT = -4,    /* leverage scores of a rank-deficient factor */
+  CPD_E_DEGENERATE = -5,        /* all sampling weights of a factor are zero */
+  CPD_E_DIVERGED = -6,          /* a factor became non-finite */
+  CPD_E_QUEUE_FULL = -7,        /* serving: admission queue is full */
+  CPD_E_NOT_FOUND = -8,         /* serving: unknown ticket */
+  CPD_E_CANCELLED = -9          /* serving: request cancelled */
+};
+
+/* Row distributions of Section 3.1 (uniform is the BrasCPD / AdasCPD arm). */
+enum { CPD_SAMPLER_UNIFORM = 0, CPD_SAMPLER_LEVERAGE = 1, CPD_SAMPLER_EUCLIDEAN = 2 };
+
+/* Step rules: fixed alpha (Algorithm 4), AdaGrad (Algorithm 5), and the
+ * decreasing alpha_t = beta / (t + gamma) of Theorem 9. */
+enum { CPD_RULE_FIXED = 0, CPD_RULE_ADAGRAD = 1, CPD_RULE_DECREASING = 2 };
+
+enum { CPD_F32 = 0, CPD_BF16 = 1, CPD_F64 = 2 };
+enum { CPD_HOST = 0, CPD_DEVICE = 1 };
+
+typedef struct cpd_problem {
+  int32_t N;                       /* number of modes, 2..CPD_MAX_MODES */
+  int32_t dims[CPD_MAX_MODES];     /* mode sizes, 1..CPD_MAX_DIM */
+  int32_t R;                       /* rank, 1..CPD_MAX_RANK */
+  int32_t B;                       /* mini-batch size |F_n|, 1..CPD_MAX_BATCH */
+  uint64_t seed;                   /* Philox key word 0 */
+  uint64_t stream_id;              /* Philox key word 1 */
+} cpd_problem;
+
+typedef struct cpd_options {
+  int32_t sampler;                 /* CPD_SAMPLER_* */
+  int32_t rule;                    /* CPD_RULE_* */
+  double alpha;                    /* fixed step */
+  double eta;                      /* AdaGrad base step */
+  double b;                        /* AdaGrad offset (0 allowed) */
+  double beta, gamma;              /* decreasing step alpha_t = beta/(t+gamma) */
+  int32_t storage;                 /* tensor storage: CPD_F32 or CPD_BF16 */
+  int32_t nonneg;                  /* 1: project the updated factor onto A >= 0 */
+  int32_t fit_every;               /* steps between fit checks (serving/batch) */
+  double fit_target;               /* stop when fit >= target (serving/batch) */
+  int64_t max_steps;               /* stop after this many steps (serving/batch) */
+} cpd_options;
+
+typedef struct cpd_handle cpd_handle;
+
+/* Thread-local message describing the last error of the calling thread. */
+CPD_API const char* cpd_last_error(void);
+
+/* Library version string. */
+CPD_API const char* cpd_version(void);
+
+/*
+ * cpd_workspace_size: device bytes that cpd_init needs for this problem
+ * (N mode-major copies of the tensor, factors, AdaGrad accumulators, CDFs,
+ * host-input staging and scratch).  Pure; no device call.
+ * Errors: CPD_E_INVALID for sizes outside the limits above.
+ */
+CPD_API cpd_status cpd_workspace_size(const cpd_problem* p, const cpd_options* o, size_t* bytes);
+
+/*
+ * cpd_init: bind a decomposition to a caller-owned device workspace.
+ *   X        dense tensor (layout above), element type x_dtype (CPD_F32 or
+ *            CPD_F64), in host memory (x_space = CPD_HOST) or on the device.
+ *            It is rounded to the storage type (FP32 round-to-nearest, then
+ *            BF16 round-to-nearest-even) and written as N copies, copy n
+ *            holding the mode-n fibres as contiguous rows (row j = the
+ *            unfolding column j of the Section 1 index map).
+ *   A0       N host pointers, A0[k] is dims[k] x R row-major FP32.
+ *   ws       device memory of at least cpd_workspace_size bytes, 256-byte
+ *            aligned; owned by the caller and must outlive the handle.
+ *   stream   hipStream_t (NULL = the default stream) on which all work of
+ *            the handle is enqueued.
+ * Returns after the tensor and factors are in ws, so X and A0 may be freed.
+ * Errors: CPD_E_INVALID, CPD_E_OOM (ws too small), CPD_E_HIP,
+ *         CPD_E_RANK_DEFICIENT / CPD_E_DEGENERATE (initial distributions).
+ */
+CPD_API cpd_status cpd_init(const cpd_problem* p, const cpd_options* o, const void* X, int32_t x_dtype,
+                    int32_t x_space, const float* const* A0, void* ws, size_t ws_bytes,
+                    void* stream, cpd_handle** out);
+
+/*
+ * cpd_sample: the mini-batch that step t would draw with the current factors
+ * (Algorithm 3): mode n, idx (device, B x (N-1) int32, row f = the sampled
+ * row indices of the modes k != n in ascending k) and p (device, B doubles,
+ * p_f = prod_k q_k(i_k)/Q_k).  No state changes.  Synchronous.
+ * Errors: CPD_E_INVALID, CPD_E_HIP, or a sticky error of the handle.
+ */
+CPD_API cpd_status cpd_sample(cpd_handle* h, uint64_t t, int32_t* mode, int32_t* idx_dev, double* p_dev);
+
+/*
+ * cpd_step: enqueue nsteps steps (t .. t+nsteps-1) on the handle's stream
+ * (one persistent launch).  Asynchronous: a non-finite factor or a sampling
+ * failure is recorded on the device and reported by the next synchronising
+ * call (cpd_sync, cpd_fit, cpd_read_*).
+ */
+CPD_API cpd_status cpd_step(cpd_handle* h, int64_t nsteps);
+
+/*
+ * cpd_step_replay: one step with caller-supplied mode and indices (device
+ * idx_dev as returned by cpd_sample); the probabilities come from the
+ * handle's current distributions.  Asynchronous like cpd_step.
+ */
+CPD_API cpd_status cpd_step_replay(cpd_handle* h, int32_t mode, const int32_t* idx_dev);
+
+/* Wait for the handle's stream; returns the handle's sticky device status. */
+CPD_API cpd_status cpd_sync(cpd_handle* h);
+
+/*
+ * cpd_fit: fit = 1 - ||X - [[A]]||^2 / ||X||^2 of the stored tensor, in FP64
+ * (Gram-Hadamard form for ||[[A]]||^2, one streaming pass for <X, [[A]]>).
+ * Synchronous.
+ */
+CPD_API cpd_status cpd_fit(cpd_handle* h, double* fit);
+
+/* Current step counter t. */
+CPD_API cpd_status cpd_get_step(cpd_handle* h, int64_t* t);
+
+/* Copy factor n (dims[n] x R FP32) to dst in host or device memory. Synchronous. */
+CPD_API cpd_status cpd_read_factors(cpd_handle* h, int32_t n, float* dst, int32_t dst_space);
+
+/* Copy the integer-valued FP64 CDF of mode n (dims[n] doubles) to host dst. */
+CPD_API cpd_status cpd_read_cdf(cpd_handle* h, int32_t n, double* dst);
+
+/*
+ * cpd_read_state / cpd_write_state: serialise {t, factors, AdaGrad
+ * accumulators} to a host buffer.  With buf == NULL, *bytes receives the
+ * size.  Writing a state recomputes the distributions, so a run resumed from
+ * a state continues bit for bit.
+ */
+CPD_API cpd_status cpd_read_state(cpd_handle* h, void* buf, size_t* bytes);
+CPD_API cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes);
+
+/* Release the handle (the workspace stays the caller's). */
+CPD_API cpd_status cpd_destroy(cpd_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPD_H */

@@ -1,0 +1,324 @@
+"""ctypes binding of libcpdmi (the C ABI declared in include/cpd.h).
+
+The functions here carry the C names and only marshal arguments: every step
+of the method runs in the library's HIP kernels.  PyTorch supplies device
+memory (the caller-owned workspace) and the HIP stream.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+import torch  # noqa: F401  (load torch's HIP runtime before the library)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpdmi.so")
+
+MAX_MODES = 8
+MAX_RANK = 64
+
+CPD_OK, CPD_PENDING = 0, 1
+CPD_E_INVALID, CPD_E_OOM, CPD_E_HIP = -1, -2, -3
+CPD_E_RANK_DEFICIENT, CPD_E_DEGENERATE, CPD_E_DIVERGED = -4, -5, -6
+CPD_E_QUEUE_FULL, CPD_E_NOT_FOUND, CPD_E_CANCELLED = -7, -8, -9
+
+SAMPLER = {"uniform": 0, "leverage": 1, "euclidean": 2}
+RULE = {"fixed": 0, "adagrad": 1, "decreasing": 2}
+CPD_F32, CPD_BF16, CPD_F64 = 0, 1, 2
+CPD_HOST, CPD_DEVICE = 0, 1
+STORAGE = {"f32": CPD_F32, "fp32": CPD_F32, "float32": CPD_F32, "bf16": CPD_BF16,
+           "bfloat16": CPD_BF16}
+
+
+class CpdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"cpd status {status}: {msg}")
+        self.status = status
+
+
+class cpd_problem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("dims", ctypes.c_int32 * MAX_MODES),
+                ("R", ctypes.c_int32), ("B", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64)]
+
+
+class cpd_options(ctypes.Structure):
+    _fields_ = [("sampler", ctypes.c_int32), ("rule", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("eta", ctypes.c_double), ("b", ctypes.c_double),
+                ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("storage", ctypes.c_int32), ("nonneg", ctypes.c_int32),
+                ("fit_every", ctypes.c_int32), ("fit_target", ctypes.c_double),
+                ("max_steps", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2103_04081_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        H = ctypes.c_void_p
+        P = ctypes.POINTER
+        st = ctypes.c_int32
+        sig = {
+            "cpd_last_error": (ctypes.c_char_p, []),
+            "cpd_version": (ctypes.c_char_p, []),
+            "cpd_workspace_size": (st, [P(cpd_problem), P(cpd_options), P(ctypes.c_size_t)]),
+            "cpd_init": (st, [P(cpd_problem), P(cpd_options), ctypes.c_void_p, ctypes.c_int32,
+                              ctypes.c_int32, P(ctypes.c_void_p), ctypes.c_void_p,
+                              ctypes.c_size_t, ctypes.c_void_p, P(H)]),
+            "cpd_sample": (st, [H, ctypes.c_uint64, P(ctypes.c_int32), ctypes.c_void_p,
+                                ctypes.c_void_p]),
+            "cpd_step": (st, [H, ctypes.c_int64]),
+            "cpd_step_replay": (st, [H, ctypes.c_int32, ctypes.c_void_p]),
+            "cpd_sync": (st, [H]),
+            "cpd_fit": (st, [H, P(ctypes.c_double)]),
+            "cpd_get_step": (st, [H, P(ctypes.c_int64)]),
+            "cpd_read_factors": (st, [H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32]),
+            "cpd_read_cdf": (st, [H, ctypes.c_int32, ctypes.c_void_p]),
+            "cpd_read_state": (st, [H, ctypes.c_void_p, P(ctypes.c_size_t)]),
+            "cpd_write_state": (st, [H, ctypes.c_void_p, ctypes.c_size_t]),
+            "cpd_destroy": (st, [H]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _extra_signatures(L)
+        _lib = L
+    return _lib
+
+
+def _extra_signatures(L):
+    """Signatures of the batched and serving entry points (if present)."""
+    H = ctypes.c_void_p
+    P = ctypes.POINTER
+    st = ctypes.c_int32
+    extra = {
+        "cpd_batch_create": (st, [P(H), ctypes.c_int32, ctypes.c_void_p, P(H)]),
+        "cpd_batch_step": (st, [H, ctypes.c_int64]),
+        "cpd_batch_fits": (st, [H, P(ctypes.c_double)]),
+        "cpd_batch_sync": (st, [H]),
+        "cpd_batch_destroy": (st, [H]),
+    }
+    for name, (res, args) in extra.items():
+        if hasattr(L, name):
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+
+
+def last_error():
+    return lib().cpd_last_error().decode()
+
+
+def check(status, what=""):
+    if status < 0:
+        raise CpdError(status, f"{what}: {last_error()}")
+    return status
+
+
+def make_problem(dims, R, B, seed=0, stream_id=0):
+    p = cpd_problem()
+    p.N = len(dims)
+    for k, d in enumerate(dims):
+        p.dims[k] = int(d)
+    p.R, p.B = int(R), int(B)
+    p.seed, p.stream_id = int(seed), int(stream_id)
+    return p
+
+
+def make_options(sampler="euclidean", rule="adagrad", alpha=0.0, eta=1.0, b=0.0, beta=0.0,
+                 gamma=1.0, storage="f32", nonneg=False, fit_every=25, fit_target=0.99,
+                 max_steps=0):
+    o = cpd_options()
+    o.sampler = SAMPLER[sampler] if isinstance(sampler, str) else int(sampler)
+    o.rule = RULE[rule] if isinstance(rule, str) else int(rule)
+    o.alpha, o.eta, o.b, o.beta, o.gamma = float(alpha), float(eta), float(b), float(beta), float(gamma)
+    o.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    o.nonneg = int(bool(nonneg))
+    o.fit_every = int(fit_every)
+    o.fit_target = float(fit_target)
+    o.max_steps = int(max_steps)
+    return o
+
+
+# --- thin wrappers with the C names ----------------------------------------
+
+def cpd_workspace_size(problem, options):
+    n = ctypes.c_size_t()
+    check(lib().cpd_workspace_size(ctypes.byref(problem), ctypes.byref(options), ctypes.byref(n)),
+          "cpd_workspace_size")
+    return n.value
+
+
+def cpd_init(problem, options, X_ptr, x_dtype, x_space, A0_list, ws_ptr, ws_bytes, stream):
+    arr = (ctypes.c_void_p * len(A0_list))(*[a.ctypes.data for a in A0_list])
+    h = ctypes.c_void_p()
+    check(lib().cpd_init(ctypes.byref(problem), ctypes.byref(options), ctypes.c_void_p(X_ptr),
+                         x_dtype, x_space, arr, ctypes.c_void_p(ws_ptr), ws_bytes,
+                         ctypes.c_void_p(stream), ctypes.byref(h)), "cpd_init")
+    return h
+
+
+def cpd_sample(h, t, idx_ptr, p_ptr):
+    mode = ctypes.c_int32()
+    check(lib().cpd_sample(h, int(t), ctypes.byref(mode), ctypes.c_void_p(idx_ptr),
+                           ctypes.c_void_p(p_ptr)), "cpd_sample")
+    return mode.value
+
+
+def cpd_step(h, nsteps):
+    return check(lib().cpd_step(h, int(nsteps)), "cpd_step")
+
+
+def cpd_step_replay(h, mode, idx_ptr):
+    return check(lib().cpd_step_replay(h, int(mode), ctypes.c_void_p(idx_ptr)), "cpd_step_replay")
+
+
+def cpd_sync(h):
+    return check(lib().cpd_sync(h), "cpd_sync")
+
+
+def cpd_fit(h):
+    f = ctypes.c_double()
+    check(lib().cpd_fit(h, ctypes.byref(f)), "cpd_fit")
+    return f.value
+
+
+def cpd_get_step(h):
+    t = ctypes.c_int64()
+    check(lib().cpd_get_step(h, ctypes.byref(t)), "cpd_get_step")
+    return t.value
+
+
+def cpd_read_factors(h, n, dst_ptr, space):
+    return check(lib().cpd_read_factors(h, int(n), ctypes.c_void_p(dst_ptr), space),
+                 "cpd_read_factors")
+
+
+def cpd_read_cdf(h, n, dst_ptr):
+    return check(lib().cpd_read_cdf(h, int(n), ctypes.c_void_p(dst_ptr)), "cpd_read_cdf")
+
+
+def cpd_read_state(h):
+    n = ctypes.c_size_t()
+    check(lib().cpd_read_state(h, None, ctypes.byref(n)), "cpd_read_state")
+    buf = ctypes.create_string_buffer(n.value)
+    check(lib().cpd_read_state(h, buf, ctypes.byref(n)), "cpd_read_state")
+    return bytes(buf.raw[:n.value])
+
+
+def cpd_write_state(h, blob):
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    return check(lib().cpd_write_state(h, buf, len(blob)), "cpd_write_state")
+
+
+def cpd_destroy(h):
+    return check(lib().cpd_destroy(h), "cpd_destroy")
+
+
+# --- convenience object -----------------------------------------------------
+
+class Decomposition:
+    """One decomposition bound to a torch-allocated device workspace.
+
+    ``X``: numpy array (any order; taken as the tensor of shape dims) or a
+    CUDA torch tensor whose memory is mode-1-fastest (shape dims[::-1],
+    C-contiguous).  ``A0``: list of dims[k] x R arrays.
+    """
+
+    def __init__(self, X, A0, *, B, R=None, sampler="euclidean", rule="adagrad", alpha=0.0,
+                 eta=1.0, b=0.0, beta=0.0, gamma=1.0, storage="f32", nonneg=False, seed=0,
+                 stream_id=0, device="cuda", dims=None):
+        self.device = torch.device(device)
+        if isinstance(X, torch.Tensor):
+            assert X.is_cuda and X.is_contiguous()
+            dims = list(dims) if dims is not None else list(X.shape[::-1])
+            x_ptr, x_space = X.data_ptr(), CPD_DEVICE
+            x_dtype = CPD_F64 if X.dtype == torch.float64 else CPD_F32
+            self._x_keep = X
+        else:
+            Xn = np.asarray(X)
+            dims = list(Xn.shape)
+            x_dtype = CPD_F64 if Xn.dtype == np.float64 else CPD_F32
+            Xf = np.asfortranarray(Xn.astype(np.float64 if x_dtype == CPD_F64 else np.float32,
+                                             copy=False))
+            x_ptr, x_space = Xf.ctypes.data, CPD_HOST
+            self._x_keep = Xf
+        self.A0 = [np.ascontiguousarray(np.asarray(a, dtype=np.float32)) for a in A0]
+        R = self.A0[0].shape[1] if R is None else int(R)
+        self.dims, self.R, self.B = dims, R, int(B)
+        self.problem = make_problem(dims, R, B, seed, stream_id)
+        self.options = make_options(sampler, rule, alpha, eta, b, beta, gamma, storage, nonneg)
+        self.ws_bytes = cpd_workspace_size(self.problem, self.options)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = cpd_init(self.problem, self.options, x_ptr, x_dtype, x_space, self.A0,
+                          self.ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+        self._x_keep = None
+
+    # calls -------------------------------------------------------------------
+    def step(self, nsteps=1):
+        cpd_step(self.h, nsteps)
+
+    def sync(self):
+        cpd_sync(self.h)
+
+    def fit(self):
+        return cpd_fit(self.h)
+
+    @property
+    def t(self):
+        return cpd_get_step(self.h)
+
+    def factors(self):
+        out = []
+        for k, I in enumerate(self.dims):
+            a = np.empty((I, self.R), dtype=np.float32)
+            cpd_read_factors(self.h, k, a.ctypes.data, CPD_HOST)
+            out.append(a)
+        return out
+
+    def cdf(self, n):
+        c = np.empty(self.dims[n], dtype=np.float64)
+        cpd_read_cdf(self.h, n, c.ctypes.data)
+        return c
+
+    def sample(self, t):
+        """(mode, idx (B x N-1 int32 numpy), p (B float64 numpy))."""
+        N = len(self.dims)
+        idx = torch.empty((self.B, N - 1), dtype=torch.int32, device=self.device)
+        p = torch.empty(self.B, dtype=torch.float64, device=self.device)
+        mode = cpd_sample(self.h, t, idx.data_ptr(), p.data_ptr())
+        return mode, idx.cpu().numpy(), p.cpu().numpy()
+
+    def step_replay(self, mode, idx):
+        idx_t = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32), device=self.device)
+        cpd_step_replay(self.h, mode, idx_t.data_ptr())
+        self.sync()
+
+    def state(self):
+        return cpd_read_state(self.h)
+
+    def load_state(self, blob):
+        cpd_write_state(self.h, blob)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            cpd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

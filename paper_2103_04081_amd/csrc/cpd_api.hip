@@ -1,0 +1,550 @@
+// C ABI of libcpdmi: single-decomposition handles.
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cpd_runtime.hpp"
+
+namespace cpdmi {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+cpd_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return CPD_E_HIP;
+}
+
+static size_t align_up(size_t a) { return (a + kAlign - 1) / kAlign * kAlign; }
+
+cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w, std::string* why) {
+  if (!p || !o || !w) {
+    *why = "null argument";
+    return CPD_E_INVALID;
+  }
+  if (p->N < 2 || p->N > kMaxModes) {
+    *why = "N must be in [2, " + std::to_string(kMaxModes) + "]";
+    return CPD_E_INVALID;
+  }
+  if (p->R < 1 || p->R > kMaxRank) {
+    *why = "R must be in [1, " + std::to_string(kMaxRank) + "]";
+    return CPD_E_INVALID;
+  }
+  if (p->B < 1 || p->B > CPD_MAX_BATCH) {
+    *why = "B must be in [1, " + std::to_string(CPD_MAX_BATCH) + "]";
+    return CPD_E_INVALID;
+  }
+  if (o->sampler < 0 || o->sampler > 2 || o->rule < 0 || o->rule > 2) {
+    *why = "unknown sampler or rule";
+    return CPD_E_INVALID;
+  }
+  if (o->storage != CPD_F32 && o->storage != CPD_BF16) {
+    *why = "storage must be CPD_F32 or CPD_BF16";
+    return CPD_E_INVALID;
+  }
+  int64_t total = 1;
+  for (int k = 0; k < p->N; ++k) {
+    if (p->dims[k] < 1 || p->dims[k] > CPD_MAX_DIM) {
+      *why = "dims must be in [1, " + std::to_string(CPD_MAX_DIM) + "]";
+      return CPD_E_INVALID;
+    }
+    total *= p->dims[k];
+    if (total > (int64_t)1 << 40) {
+      *why = "tensor too large";
+      return CPD_E_INVALID;
+    }
+  }
+  const size_t es = o->storage == CPD_BF16 ? 2 : 4;
+  size_t off = 0;
+  w->state = off;
+  off = align_up(off + sizeof(ChainState) + 64);
+  w->desc = off;
+  off = align_up(off + sizeof(ChainDesc));
+  w->parts = off;
+  off = align_up(off + sizeof(double) * kFitParts);
+  for (int k = 0; k < p->N; ++k) {
+    const size_t fb = sizeof(float) * (size_t)p->dims[k] * p->R;
+    w->A[k] = off;
+    off = align_up(off + fb);
+    w->S[k] = off;
+    off = align_up(off + fb);
+    w->C[k] = off;
+    off = align_up(off + sizeof(double) * p->dims[k]);
+  }
+  for (int n = 0; n < p->N; ++n) {
+    w->ld[n] = (int32_t)round_up(p->dims[n], kLdAlign);
+    w->rows[n] = total / p->dims[n];
+    w->X[n] = off;
+    off = align_up(off + es * (size_t)w->rows[n] * w->ld[n]);
+  }
+  w->total = off;
+  const LdsPlan lp = lds_plan(p->N, p->dims, p->R, p->B);
+  w->lds = lp.total;
+  if (w->lds > 160 * 1024) {
+    *why = "problem needs " + std::to_string(w->lds) +
+           " bytes of LDS per workgroup (limit 163840): reduce B, R or the mode sizes";
+    return CPD_E_INVALID;
+  }
+  return CPD_OK;
+}
+
+void fill_desc(const cpd_problem* p, const cpd_options* o, const WsPlan& w, char* base,
+               ChainDesc* d) {
+  std::memset(d, 0, sizeof(*d));
+  d->N = p->N;
+  d->R = p->R;
+  d->B = p->B;
+  d->RT = (p->R + 15) / 16;
+  for (int k = 0; k < p->N; ++k) {
+    d->dims[k] = p->dims[k];
+    d->ld[k] = w.ld[k];
+    d->ksplit[k] = host_ksplit(p->dims[k], o->storage, p->B);
+    d->X[k] = base + w.X[k];
+    d->A[k] = (float*)(base + w.A[k]);
+    d->S[k] = (float*)(base + w.S[k]);
+    d->C[k] = (double*)(base + w.C[k]);
+  }
+  d->dtype = o->storage;
+  d->sampler = o->sampler;
+  d->rule = o->rule;
+  d->nonneg = o->nonneg;
+  d->alpha = (float)o->alpha;
+  d->eta = (float)o->eta;
+  d->b = (float)o->b;
+  d->beta = o->beta;
+  d->gamma = o->gamma;
+  d->key0 = p->seed;
+  d->key1 = p->stream_id;
+  d->state = (ChainState*)(base + w.state);
+  d->parts = (double*)(base + w.parts);
+  d->active = 1;
+  d->step_limit = 0;
+}
+
+}  // namespace cpdmi
+
+using namespace cpdmi;
+
+struct cpd_handle {
+  cpd_problem p;
+  cpd_options o;
+  int device;
+  hipStream_t stream;
+  char* ws;
+  WsPlan plan;
+  ChainDesc desc;       // host mirror of the device descriptor
+  ChainDesc* d_desc;    // in the workspace
+  int32_t* d_mode;      // scratch int in the state block
+};
+
+static cpd_status read_state(cpd_handle* h, ChainState* st) {
+  hipError_t e = hipMemcpyAsync(st, h->ws + h->plan.state, sizeof(ChainState), hipMemcpyDeviceToHost,
+                                h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state)");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return CPD_OK;
+}
+
+static cpd_status device_status(cpd_handle* h) {
+  ChainState st;
+  cpd_status s = read_state(h, &st);
+  if (s != CPD_OK) return s;
+  if (st.status != 0) {
+    switch (st.status) {
+      case CPD_E_RANK_DEFICIENT: set_error("a factor is rank deficient (leverage scores undefined)"); break;
+      case CPD_E_DEGENERATE: set_error("all sampling weights of a factor are zero or not finite"); break;
+      case CPD_E_DIVERGED: set_error("a factor became non-finite (step too large?)"); break;
+      default: set_error("device error " + std::to_string(st.status));
+    }
+  }
+  return st.status;
+}
+
+static cpd_status set_device(cpd_handle* h) {
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return CPD_OK;
+}
+
+extern "C" {
+
+const char* cpd_last_error(void) { return g_last_error.c_str(); }
+
+const char* cpd_version(void) { return "libcpdmi 0.1 (gfx950)"; }
+
+cpd_status cpd_workspace_size(const cpd_problem* p, const cpd_options* o, size_t* bytes) {
+  try {
+    if (!bytes) {
+      set_error("bytes is null");
+      return CPD_E_INVALID;
+    }
+    WsPlan w;
+    std::string why;
+    cpd_status s = plan_workspace(p, o, &w, &why);
+    if (s != CPD_OK) {
+      set_error(why);
+      return s;
+    }
+    *bytes = w.total;
+    return CPD_OK;
+  } catch (...) {
+    set_error("unexpected exception");
+    return CPD_E_INVALID;
+  }
+}
+
+cpd_status cpd_init(const cpd_problem* p, const cpd_options* o, const void* X, int32_t x_dtype,
+                    int32_t x_space, const float* const* A0, void* ws, size_t ws_bytes,
+                    void* stream, cpd_handle** out) {
+  try {
+    if (!out || !X || !A0 || !ws) {
+      set_error("null argument");
+      return CPD_E_INVALID;
+    }
+    *out = nullptr;
+    WsPlan w;
+    std::string why;
+    cpd_status s = plan_workspace(p, o, &w, &why);
+    if (s != CPD_OK) {
+      set_error(why);
+      return s;
+    }
+    if (x_dtype != CPD_F32 && x_dtype != CPD_F64) {
+      set_error("x_dtype must be CPD_F32 or CPD_F64");
+      return CPD_E_INVALID;
+    }
+    if (x_space != CPD_HOST && x_space != CPD_DEVICE) {
+      set_error("x_space must be CPD_HOST or CPD_DEVICE");
+      return CPD_E_INVALID;
+    }
+    if (((uintptr_t)ws) % kAlign) {
+      set_error("workspace must be 256-byte aligned");
+      return CPD_E_INVALID;
+    }
+    if (ws_bytes < w.total) {
+      set_error("workspace too small: need " + std::to_string(w.total) + " bytes");
+      return CPD_E_OOM;
+    }
+    for (int k = 0; k < p->N; ++k)
+      if (!A0[k]) {
+        set_error("null initial factor");
+        return CPD_E_INVALID;
+      }
+    cpd_handle* h = new (std::nothrow) cpd_handle();
+    if (!h) {
+      set_error("out of host memory");
+      return CPD_E_OOM;
+    }
+    h->p = *p;
+    h->o = *o;
+    h->stream = (hipStream_t)stream;
+    h->ws = (char*)ws;
+    h->plan = w;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+      delete h;
+      return hip_fail(e, "hipGetDevice");
+    }
+    fill_desc(p, o, w, h->ws, &h->desc);
+    h->d_desc = (ChainDesc*)(h->ws + w.desc);
+    h->d_mode = (int32_t*)(h->ws + w.state + sizeof(ChainState));
+    auto fail = [&](hipError_t err, const char* what) {
+      cpd_status r = hip_fail(err, what);
+      (void)hipStreamSynchronize(h->stream);
+      delete h;
+      return r;
+    };
+    e = hipMemsetAsync(ws, 0, w.total, h->stream);
+    if (e != hipSuccess) return fail(e, "hipMemsetAsync(workspace)");
+    e = hipMemcpyAsync(h->d_desc, &h->desc, sizeof(ChainDesc), hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return fail(e, "hipMemcpyAsync(desc)");
+    for (int k = 0; k < p->N; ++k) {
+      e = hipMemcpyAsync(h->desc.A[k], A0[k], sizeof(float) * (size_t)p->dims[k] * p->R,
+                         hipMemcpyHostToDevice, h->stream);
+      if (e != hipSuccess) return fail(e, "hipMemcpyAsync(A0)");
+    }
+    if (x_space == CPD_DEVICE) {
+      e = launch_layout_from_dense(X, x_dtype, h->desc, h->stream);
+      if (e != hipSuccess) return fail(e, "layout kernels");
+    } else {
+      // host input: round to the storage type on the host, copy 0 by rows
+      const int I0 = p->dims[0];
+      const int64_t rows = w.rows[0];
+      const size_t es = o->storage == CPD_BF16 ? 2 : 4;
+      const int64_t chunk = std::max<int64_t>(1, ((int64_t)8 << 20) / ((int64_t)I0 * es));
+      std::vector<unsigned char> buf((size_t)std::min(chunk, rows) * I0 * es);
+      for (int64_t r0 = 0; r0 < rows; r0 += chunk) {
+        const int64_t nr = std::min(chunk, rows - r0);
+        const int64_t base = r0 * I0, cnt = nr * I0;
+        for (int64_t i = 0; i < cnt; ++i) {
+          const float v = x_dtype == CPD_F64 ? (float)((const double*)X)[base + i]
+                                             : ((const float*)X)[base + i];
+          if (es == 2) ((uint16_t*)buf.data())[i] = f32_to_bf16_rne(v);
+          else ((float*)buf.data())[i] = v;
+        }
+        e = hipMemcpy2DAsync((char*)h->desc.X[0] + (size_t)r0 * w.ld[0] * es, (size_t)w.ld[0] * es,
+                             buf.data(), (size_t)I0 * es, (size_t)I0 * es, (size_t)nr,
+                             hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) return fail(e, "hipMemcpy2DAsync(X)");
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return fail(e, "hipStreamSynchronize");
+      }
+      e = launch_layout_from_copy0(h->desc, h->stream);
+      if (e != hipSuccess) return fail(e, "layout kernels");
+    }
+    StepArgs a{};
+    a.op = OP_REFRESH;
+    e = launch_chain_kernel(h->d_desc, 1, w.lds, a, h->stream);
+    if (e != hipSuccess) return fail(e, "refresh kernel");
+    e = launch_fit(h->d_desc, 1, o->storage, p->dims[0], p->R, false, h->stream);
+    if (e != hipSuccess) return fail(e, "norm kernels");
+    s = device_status(h);
+    if (s != CPD_OK) {
+      delete h;
+      return s;
+    }
+    *out = h;
+    return CPD_OK;
+  } catch (...) {
+    set_error("unexpected exception in cpd_init");
+    return CPD_E_INVALID;
+  }
+}
+
+cpd_status cpd_sample(cpd_handle* h, uint64_t t, int32_t* mode, int32_t* idx_dev, double* p_dev) {
+  if (!h || !mode || !idx_dev || !p_dev) {
+    set_error("null argument");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  StepArgs a{};
+  a.op = OP_SAMPLE;
+  a.sample_t = t;
+  a.out_idx = idx_dev;
+  a.out_p = p_dev;
+  a.out_mode = h->d_mode;
+  hipError_t e = launch_chain_kernel(h->d_desc, 1, h->plan.lds, a, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "sample kernel");
+  e = hipMemcpyAsync(mode, h->d_mode, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(mode)");
+  return device_status(h);
+}
+
+cpd_status cpd_step(cpd_handle* h, int64_t nsteps) {
+  if (!h || nsteps < 0) {
+    set_error("bad argument");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  const int64_t chunk = (int64_t)1 << 20;
+  for (int64_t done = 0; done < nsteps; done += chunk) {
+    StepArgs a{};
+    a.op = OP_STEP;
+    a.nsteps = std::min(chunk, nsteps - done);
+    hipError_t e = launch_chain_kernel(h->d_desc, 1, h->plan.lds, a, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "step kernel");
+  }
+  return CPD_OK;
+}
+
+cpd_status cpd_step_replay(cpd_handle* h, int32_t mode, const int32_t* idx_dev) {
+  if (!h || !idx_dev || mode < 0 || mode >= h->p.N) {
+    set_error("bad argument");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  StepArgs a{};
+  a.op = OP_REPLAY;
+  a.replay_mode = mode;
+  a.replay_idx = idx_dev;
+  hipError_t e = launch_chain_kernel(h->d_desc, 1, h->plan.lds, a, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "replay kernel");
+  return CPD_OK;
+}
+
+cpd_status cpd_sync(cpd_handle* h) {
+  if (!h) {
+    set_error("null handle");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  return device_status(h);
+}
+
+cpd_status cpd_fit(cpd_handle* h, double* fit) {
+  if (!h || !fit) {
+    set_error("null argument");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  hipError_t e = launch_fit(h->d_desc, 1, h->o.storage, h->p.dims[0], h->p.R, true, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "fit kernels");
+  ChainState st;
+  s = read_state(h, &st);
+  if (s != CPD_OK) return s;
+  *fit = st.fit;
+  if (st.status != 0) return device_status(h);
+  return CPD_OK;
+}
+
+cpd_status cpd_get_step(cpd_handle* h, int64_t* t) {
+  if (!h || !t) {
+    set_error("null argument");
+    return CPD_E_INVALID;
+  }
+  ChainState st;
+  cpd_status s = read_state(h, &st);
+  if (s != CPD_OK) return s;
+  *t = st.t;
+  return CPD_OK;
+}
+
+cpd_status cpd_read_factors(cpd_handle* h, int32_t n, float* dst, int32_t dst_space) {
+  if (!h || !dst || n < 0 || n >= h->p.N) {
+    set_error("bad argument");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  hipError_t e = hipMemcpyAsync(dst, h->desc.A[n], sizeof(float) * (size_t)h->p.dims[n] * h->p.R,
+                                dst_space == CPD_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(factor)");
+  return device_status(h);
+}
+
+cpd_status cpd_read_cdf(cpd_handle* h, int32_t n, double* dst) {
+  if (!h || !dst || n < 0 || n >= h->p.N) {
+    set_error("bad argument");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  hipError_t e = hipMemcpyAsync(dst, h->desc.C[n], sizeof(double) * (size_t)h->p.dims[n],
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(cdf)");
+  return device_status(h);
+}
+
+struct StateHeader {
+  char magic[8];
+  int32_t version, N, R, pad;
+  int32_t dims[kMaxModes];
+  int64_t t;
+};
+
+static size_t state_bytes(const cpd_handle* h) {
+  size_t n = sizeof(StateHeader);
+  for (int k = 0; k < h->p.N; ++k) n += 2 * sizeof(float) * (size_t)h->p.dims[k] * h->p.R;
+  return n;
+}
+
+cpd_status cpd_read_state(cpd_handle* h, void* buf, size_t* bytes) {
+  if (!h || !bytes) {
+    set_error("null argument");
+    return CPD_E_INVALID;
+  }
+  const size_t need = state_bytes(h);
+  if (!buf) {
+    *bytes = need;
+    return CPD_OK;
+  }
+  if (*bytes < need) {
+    *bytes = need;
+    set_error("state buffer too small");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  ChainState st;
+  s = read_state(h, &st);
+  if (s != CPD_OK) return s;
+  StateHeader hd{};
+  std::memcpy(hd.magic, "CPDSTATE", 8);
+  hd.version = 1;
+  hd.N = h->p.N;
+  hd.R = h->p.R;
+  for (int k = 0; k < h->p.N; ++k) hd.dims[k] = h->p.dims[k];
+  hd.t = st.t;
+  char* out = (char*)buf;
+  std::memcpy(out, &hd, sizeof hd);
+  size_t off = sizeof hd;
+  for (int k = 0; k < h->p.N; ++k) {
+    const size_t fb = sizeof(float) * (size_t)h->p.dims[k] * h->p.R;
+    hipError_t e = hipMemcpyAsync(out + off, h->desc.A[k], fb, hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state A)");
+    off += fb;
+    e = hipMemcpyAsync(out + off, h->desc.S[k], fb, hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state S)");
+    off += fb;
+  }
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  *bytes = need;
+  return CPD_OK;
+}
+
+cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes) {
+  if (!h || !buf) {
+    set_error("null argument");
+    return CPD_E_INVALID;
+  }
+  const size_t need = state_bytes(h);
+  StateHeader hd;
+  if (bytes < need) {
+    set_error("state buffer too small");
+    return CPD_E_INVALID;
+  }
+  std::memcpy(&hd, buf, sizeof hd);
+  if (std::memcmp(hd.magic, "CPDSTATE", 8) != 0 || hd.version != 1 || hd.N != h->p.N ||
+      hd.R != h->p.R) {
+    set_error("state does not match this problem");
+    return CPD_E_INVALID;
+  }
+  for (int k = 0; k < h->p.N; ++k)
+    if (hd.dims[k] != h->p.dims[k]) {
+      set_error("state does not match this problem");
+      return CPD_E_INVALID;
+    }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  const char* in = (const char*)buf;
+  size_t off = sizeof hd;
+  for (int k = 0; k < h->p.N; ++k) {
+    const size_t fb = sizeof(float) * (size_t)h->p.dims[k] * h->p.R;
+    hipError_t e = hipMemcpyAsync(h->desc.A[k], in + off, fb, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state A)");
+    off += fb;
+    e = hipMemcpyAsync(h->desc.S[k], in + off, fb, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state S)");
+    off += fb;
+  }
+  ChainState st{};
+  st.t = hd.t;
+  hipError_t e = hipMemcpyAsync(h->ws + h->plan.state, &st, sizeof(int64_t) + sizeof(int32_t),
+                                hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state t)");
+  StepArgs a{};
+  a.op = OP_REFRESH;
+  e = launch_chain_kernel(h->d_desc, 1, h->plan.lds, a, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "refresh kernel");
+  return device_status(h);
+}
+
+cpd_status cpd_destroy(cpd_handle* h) {
+  if (!h) return CPD_OK;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+  return CPD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+// Internal definitions shared by the host runtime and the gfx950 kernels of
+// libcpdmi: the per-decomposition descriptor read by the kernels, the
+// workspace layout, the Philox4x64-10 generator and small device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/cpd.h"
+
+namespace cpdmi {
+
+constexpr int kMaxModes = CPD_MAX_MODES;
+constexpr int kMaxRank = CPD_MAX_RANK;
+constexpr int kBlock = 512;             // threads of the persistent step workgroup
+constexpr int kWaves = kBlock / 64;
+constexpr int kFitBlock = 256;
+constexpr int kFitParts = 4096;         // partial sums of the fit / norm kernels
+constexpr size_t kAlign = 256;
+constexpr int kLdAlign = 64;            // copy rows padded to 64 elements
+constexpr double kRankTol = 1e-12;      // Cholesky pivot^2 <= tol * diagonal => rank deficient
+
+enum Op : int32_t { OP_STEP = 0, OP_SAMPLE = 1, OP_REPLAY = 2, OP_REFRESH = 3 };
+
+// Device-resident state of one decomposition (first bytes of its workspace).
+struct ChainState {
+  int64_t t;          // steps taken
+  int32_t status;     // sticky cpd_status of the device side
+  int32_t pad0;
+  double fit;         // last fit computed
+  double x2;          // ||X||^2 of the stored tensor
+  double inner;       // last <X, [[A]]>
+  double xhat2;       // last ||[[A]]||^2
+};
+
+// Everything a kernel needs to run one decomposition.  Lives in device
+// memory (inside the workspace); the batched and served paths keep arrays
+// of these.
+struct ChainDesc {
+  int32_t N, R, B, RT;                 // RT = ceil(R / 16) MFMA row tiles
+  int32_t dims[kMaxModes];
+  int32_t ld[kMaxModes];               // row stride (elements) of copy n
+  int32_t ksplit[kMaxModes];           // K-split of the contraction per mode
+  int32_t dtype;                       // CPD_F32 or CPD_BF16 storage
+  int32_t sampler, rule, nonneg;
+  float alpha, eta, b;
+  float pad1;
+  double beta, gamma;
+  uint64_t key0, key1;
+  const void* X[kMaxModes];            // copy n: J_n rows x ld[n]
+  float* A[kMaxModes];                 // factor k: dims[k] x R row-major
+  float* S[kMaxModes];                 // AdaGrad accumulators, same shape
+  double* C[kMaxModes];                // integer-valued CDF of mode k
+  ChainState* state;
+  double* parts;                       // kFitParts partial sums (fit / norm)
+  int32_t active;                      // batched path: 0 = slot idle
+  int32_t pad2;
+  int64_t step_limit;                  // batched path: stop at this t
+};
+
+struct StepArgs {
+  int64_t nsteps;
+  int32_t op;
+  int32_t replay_mode;
+  uint64_t sample_t;
+  const int32_t* replay_idx;
+  int32_t* out_idx;
+  double* out_p;
+  int32_t* out_mode;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11).  Step t, draw d uses counter
+// (t, d / 4, 0, 0) under key (seed, stream_id) and output word d % 4.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
+
+__host__ __device__ inline uint64_t mulhi_u64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+__host__ __device__ inline void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                              uint64_t k0, uint64_t k1, uint64_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += kPhiloxW0;
+      k1 += kPhiloxW1;
+    }
+    const uint64_t lo0 = kPhiloxM0 * c0, hi0 = mulhi_u64(kPhiloxM0, c0);
+    const uint64_t lo1 = kPhiloxM1 * c2, hi1 = mulhi_u64(kPhiloxM1, c2);
+    const uint64_t y0 = hi1 ^ c1 ^ k0, y2 = hi0 ^ c3 ^ k1;
+    c0 = y0;
+    c1 = lo1;
+    c2 = y2;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+__host__ __device__ inline int bit_length_u32(uint32_t v) {
+  int n = 0;
+  while (v) {
+    ++n;
+    v >>= 1;
+  }
+  return n;
+}
+
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Round an FP32 value to bfloat16, ties to even (NaN kept quiet).
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+
+// Per-mode contraction split: the I_n x R output is cut into column tiles of
+// 16 * VW entries (VW = 1 for FP32, 2 for BF16 storage), one tile per wave;
+// with fewer than 16 tiles the B dimension is split so up to 16 waves work.
+inline int host_ksplit(int In, int dtype, int B) {
+  const int vw = dtype == CPD_BF16 ? 2 : 1;
+  const int nst = (In + 16 * vw - 1) / (16 * vw);
+  if (nst >= kWaves) return 1;
+  int ks = kWaves / nst;
+  const int ksteps = (B + 3) / 4;
+  if (ks > ksteps) ks = ksteps;
+  return ks < 1 ? 1 : ks;
+}
+
+// LDS layout of the persistent step kernel for one descriptor.
+struct LdsPlan {
+  size_t cdf, idx, words, wf, rowoff, hb, gs, mbuf, part, red, wts, misc, total;
+  int rp16, bpad, ms, imax, sumdims, nd;
+};
+
+__host__ __device__ inline LdsPlan lds_plan(int N, const int32_t* dims, int R, int B) {
+  LdsPlan p;
+  p.rp16 = ((R + 15) / 16) * 16;
+  p.bpad = ((B + 3) / 4) * 4;
+  p.ms = p.rp16 + 1;
+  p.imax = 0;
+  p.sumdims = 0;
+  for (int k = 0; k < N; ++k) {
+    p.imax = dims[k] > p.imax ? dims[k] : p.imax;
+    p.sumdims += dims[k];
+  }
+  p.nd = 1 + (N - 1) * B;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (size_t)round_up((int64_t)bytes, 16);
+    return o;
+  };
+  p.cdf = take(sizeof(double) * p.sumdims);
+  p.idx = take(sizeof(int32_t) * (size_t)B * (N - 1));
+  p.words = take(sizeof(uint64_t) * (size_t)round_up(p.nd, 4));
+  p.wf = take(sizeof(double) * p.bpad);
+  p.rowoff = take(sizeof(int64_t) * p.bpad);
+  p.hb = take(sizeof(float) * (size_t)p.bpad * p.rp16);
+  p.gs = take(sizeof(double) * (size_t)R * R);
+  p.mbuf = take(sizeof(float) * (size_t)p.imax * p.ms);
+  p.part = take(sizeof(double) * (size_t)(R * R > kBlock ? R * R : kBlock));
+  p.red = take(sizeof(double) * kWaves);
+  p.wts = take(sizeof(double) * (size_t)p.imax);
+  p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
+  p.total = off;
+  return p;
+}
+
+}  // namespace cpdmi

@@ -1,0 +1,41 @@
+// Host-side runtime pieces shared by the single-decomposition API, the
+// batched path and the server: workspace planning and kernel launchers.
+#pragma once
+
+#include <string>
+
+#include "cpd_internal.hpp"
+
+namespace cpdmi {
+
+hipError_t launch_chain_kernel(const ChainDesc* descs, int nchains, size_t lds_bytes,
+                               const StepArgs& args, hipStream_t stream);
+hipError_t launch_layout_from_dense(const void* X, int in_dtype, const ChainDesc& d,
+                                    hipStream_t stream);
+hipError_t launch_layout_from_copy0(const ChainDesc& d, hipStream_t stream);
+hipError_t launch_fit(const ChainDesc* d_descs, int nchains, int dtype, int max_I0, int max_R,
+                      bool inner, hipStream_t stream);
+
+// Offsets of every region of one decomposition's workspace.
+struct WsPlan {
+  size_t state, desc, parts;
+  size_t A[kMaxModes], S[kMaxModes], C[kMaxModes];
+  size_t X[kMaxModes];
+  int32_t ld[kMaxModes];
+  int64_t rows[kMaxModes];  // J_n
+  size_t total;
+  size_t lds;               // dynamic LDS of the step kernel
+};
+
+// Validates the problem; returns CPD_OK or CPD_E_INVALID with a message.
+cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* out,
+                          std::string* why);
+
+// Fill a descriptor for a workspace at `base` (device address).
+void fill_desc(const cpd_problem* p, const cpd_options* o, const WsPlan& w, char* base,
+               ChainDesc* d);
+
+void set_error(const std::string& msg);
+cpd_status hip_fail(hipError_t e, const char* what);
+
+}  // namespace cpdmi
