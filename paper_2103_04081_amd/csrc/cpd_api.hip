@@ -77,10 +77,15 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
     w->ld[n] = (int32_t)round_up(p->dims[n], kLdAlign);
     w->rows[n] = total / p->dims[n];
     w->X[n] = off;
-    off = align_up(off + es * (size_t)w->rows[n] * w->ld[n]);
+    const size_t copy_bytes = es * (size_t)w->rows[n] * w->ld[n];
+    if (copy_bytes > ((size_t)1 << 32) - 256) {
+      *why = "each mode-major copy of the tensor must stay below 4 GiB";
+      return CPD_E_INVALID;
+    }
+    off = align_up(off + copy_bytes);
   }
   w->total = off;
-  const LdsPlan lp = lds_plan(p->N, p->dims, p->R, p->B);
+  const LdsPlan lp = lds_plan(p->N, p->dims, p->R, p->B, (p->R + 15) / 16);
   w->lds = lp.total;
   if (w->lds > 160 * 1024) {
     *why = "problem needs " + std::to_string(w->lds) +
@@ -100,7 +105,7 @@ void fill_desc(const cpd_problem* p, const cpd_options* o, const WsPlan& w, char
   for (int k = 0; k < p->N; ++k) {
     d->dims[k] = p->dims[k];
     d->ld[k] = w.ld[k];
-    d->ksplit[k] = host_ksplit(p->dims[k], o->storage, p->B);
+    d->ksplit[k] = host_ksplit(p->dims[k], o->storage, p->B, p->R);
     d->X[k] = base + w.X[k];
     d->A[k] = (float*)(base + w.A[k]);
     d->S[k] = (float*)(base + w.S[k]);
@@ -297,7 +302,7 @@ cpd_status cpd_init(const cpd_problem* p, const cpd_options* o, const void* X, i
     }
     StepArgs a{};
     a.op = OP_REFRESH;
-    e = launch_chain_kernel(h->d_desc, 1, w.lds, a, h->stream);
+    e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, w.lds, a, h->stream);
     if (e != hipSuccess) return fail(e, "refresh kernel");
     e = launch_fit(h->d_desc, 1, o->storage, p->dims[0], p->R, false, h->stream);
     if (e != hipSuccess) return fail(e, "norm kernels");
@@ -327,7 +332,7 @@ cpd_status cpd_sample(cpd_handle* h, uint64_t t, int32_t* mode, int32_t* idx_dev
   a.out_idx = idx_dev;
   a.out_p = p_dev;
   a.out_mode = h->d_mode;
-  hipError_t e = launch_chain_kernel(h->d_desc, 1, h->plan.lds, a, h->stream);
+  hipError_t e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
   if (e != hipSuccess) return hip_fail(e, "sample kernel");
   e = hipMemcpyAsync(mode, h->d_mode, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(mode)");
@@ -346,7 +351,7 @@ cpd_status cpd_step(cpd_handle* h, int64_t nsteps) {
     StepArgs a{};
     a.op = OP_STEP;
     a.nsteps = std::min(chunk, nsteps - done);
-    hipError_t e = launch_chain_kernel(h->d_desc, 1, h->plan.lds, a, h->stream);
+    hipError_t e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
     if (e != hipSuccess) return hip_fail(e, "step kernel");
   }
   return CPD_OK;
@@ -363,7 +368,7 @@ cpd_status cpd_step_replay(cpd_handle* h, int32_t mode, const int32_t* idx_dev) 
   a.op = OP_REPLAY;
   a.replay_mode = mode;
   a.replay_idx = idx_dev;
-  hipError_t e = launch_chain_kernel(h->d_desc, 1, h->plan.lds, a, h->stream);
+  hipError_t e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
   if (e != hipSuccess) return hip_fail(e, "replay kernel");
   return CPD_OK;
 }
@@ -534,7 +539,7 @@ cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes) {
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state t)");
   StepArgs a{};
   a.op = OP_REFRESH;
-  e = launch_chain_kernel(h->d_desc, 1, h->plan.lds, a, h->stream);
+  e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
   if (e != hipSuccess) return hip_fail(e, "refresh kernel");
   return device_status(h);
 }

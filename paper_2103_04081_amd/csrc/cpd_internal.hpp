@@ -19,7 +19,10 @@ constexpr int kFitBlock = 256;
 constexpr int kFitParts = 4096;         // partial sums of the fit / norm kernels
 constexpr size_t kAlign = 256;
 constexpr int kLdAlign = 64;            // copy rows padded to 64 elements
+constexpr int kChunkSteps = 32;         // MFMA K-steps (4 fibres each) per chunk, for VW = RT = 1
+constexpr int kFibrePad = 4 * kChunkSteps;  // sampled fibres padded (zero weight) to full chunks
 constexpr double kRankTol = 1e-12;      // Cholesky pivot^2 <= tol * diagonal => rank deficient
+constexpr size_t kLdsBudget = 160 * 1024;  // LDS per workgroup on gfx950
 
 enum Op : int32_t { OP_STEP = 0, OP_SAMPLE = 1, OP_REPLAY = 2, OP_REFRESH = 3 };
 
@@ -120,6 +123,16 @@ __host__ __device__ inline int bit_length_u32(uint32_t v) {
 
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// Pointers read from a descriptor are generic; accesses through them would
+// be FLAT instructions, which also count against the LDS wait counter and so
+// serialise LDS reads behind outstanding HBM loads.  gmem() marks them as
+// global memory.
+#define CPD_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ CPD_GLOBAL T* gmem(T* p) {
+  return (CPD_GLOBAL T*)(p);
+}
+
 // Round an FP32 value to bfloat16, ties to even (NaN kept quiet).
 __host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
   uint32_t u;
@@ -138,27 +151,32 @@ __host__ __device__ inline float bf16_to_f32(uint16_t h) {
 
 // Per-mode contraction split: the I_n x R output is cut into column tiles of
 // 16 * VW entries (VW = 1 for FP32, 2 for BF16 storage), one tile per wave;
-// with fewer than 16 tiles the B dimension is split so up to 16 waves work.
-inline int host_ksplit(int In, int dtype, int B) {
+// with fewer tiles than waves the B dimension is split as well.
+inline int host_ksplit(int In, int dtype, int B, int R) {
   const int vw = dtype == CPD_BF16 ? 2 : 1;
   const int nst = (In + 16 * vw - 1) / (16 * vw);
   if (nst >= kWaves) return 1;
   int ks = kWaves / nst;
-  const int ksteps = (B + 3) / 4;
-  if (ks > ksteps) ks = ksteps;
+  const int rt = (R + 15) / 16;
+  const int u = kChunkSteps / vw / rt;  // K-steps per chunk of the contraction
+  const int chunks = (int)(((B + kFibrePad - 1) / kFibrePad) * kFibrePad / 4 / u);
+  if (ks > chunks) ks = chunks;
   return ks < 1 ? 1 : ks;
 }
 
-// LDS layout of the persistent step kernel for one descriptor.
+// LDS layout of the persistent step kernel for one descriptor, compiled for
+// RT 16-row rank tiles (RT >= ceil(R / 16)).
 struct LdsPlan {
-  size_t cdf, idx, words, wf, rowoff, hb, gs, mbuf, part, red, wts, misc, total;
-  int rp16, bpad, ms, imax, sumdims, nd;
+  size_t cdf, idx, ratio, words, wf, rinv, rowoff, wht, gs, gsp, mbuf, gram, part, red, wts,
+      misc, sbuf, total;
+  int rp16, bpad, ms, imax, sumdims, nd, nblk;
+  int has_sbuf;  // AdaGrad accumulators of the updated mode staged in LDS
 };
 
-__host__ __device__ inline LdsPlan lds_plan(int N, const int32_t* dims, int R, int B) {
+__host__ __device__ inline LdsPlan lds_plan(int N, const int32_t* dims, int R, int B, int RT) {
   LdsPlan p;
-  p.rp16 = ((R + 15) / 16) * 16;
-  p.bpad = ((B + 3) / 4) * 4;
+  p.rp16 = 16 * RT;
+  p.bpad = ((B + kFibrePad - 1) / kFibrePad) * kFibrePad;
   p.ms = p.rp16 + 1;
   p.imax = 0;
   p.sumdims = 0;
@@ -167,6 +185,8 @@ __host__ __device__ inline LdsPlan lds_plan(int N, const int32_t* dims, int R, i
     p.sumdims += dims[k];
   }
   p.nd = 1 + (N - 1) * B;
+  p.nblk = (p.nd + 3) / 4;
+  const int t2 = RT * RT;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -175,16 +195,27 @@ __host__ __device__ inline LdsPlan lds_plan(int N, const int32_t* dims, int R, i
   };
   p.cdf = take(sizeof(double) * p.sumdims);
   p.idx = take(sizeof(int32_t) * (size_t)B * (N - 1));
-  p.words = take(sizeof(uint64_t) * (size_t)round_up(p.nd, 4));
-  p.wf = take(sizeof(double) * p.bpad);
-  p.rowoff = take(sizeof(int64_t) * p.bpad);
-  p.hb = take(sizeof(float) * (size_t)p.bpad * p.rp16);
-  p.gs = take(sizeof(double) * (size_t)R * R);
+  p.ratio = take(sizeof(double) * (size_t)B * (N - 1));
+  p.words = take(sizeof(uint64_t) * 4 * (size_t)p.nblk);
+  p.wf = take(sizeof(float) * p.bpad);
+  p.rinv = take(sizeof(float) * p.bpad);
+  p.rowoff = take(sizeof(uint32_t) * p.bpad);
+  p.wht = take(sizeof(float) * (size_t)p.bpad * p.rp16);
+  p.gs = take(sizeof(float) * (size_t)p.rp16 * p.rp16);
   p.mbuf = take(sizeof(float) * (size_t)p.imax * p.ms);
-  p.part = take(sizeof(double) * (size_t)(R * R > kBlock ? R * R : kBlock));
-  p.red = take(sizeof(double) * kWaves);
+  p.gram = take(sizeof(double) * (size_t)R * R);
+  // Gs partials (Gs phase) and the Gram partials (leverage refresh) share
+  const size_t gsp_bytes = sizeof(float) * 256 * (size_t)(t2 > kWaves ? t2 : kWaves);
+  const size_t part_bytes = sizeof(double) * kBlock;
+  p.part = take(gsp_bytes > part_bytes ? gsp_bytes : part_bytes);
+  p.gsp = p.part;
+  p.red = take(sizeof(double) * 2 * kWaves);
   p.wts = take(sizeof(double) * (size_t)p.imax);
   p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
+  // the AdaGrad accumulators of the mode being updated, when they fit
+  const size_t sbytes = sizeof(float) * (size_t)p.imax * p.ms;
+  p.has_sbuf = off + sbytes <= kLdsBudget;
+  p.sbuf = p.has_sbuf ? take(sbytes) : 0;
   p.total = off;
   return p;
 }

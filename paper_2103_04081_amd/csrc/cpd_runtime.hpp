@@ -8,7 +8,7 @@
 
 namespace cpdmi {
 
-hipError_t launch_chain_kernel(const ChainDesc* descs, int nchains, size_t lds_bytes,
+hipError_t launch_chain_kernel(const ChainDesc* descs, int nchains, int rt, size_t lds_bytes,
                                const StepArgs& args, hipStream_t stream);
 hipError_t launch_layout_from_dense(const void* X, int in_dtype, const ChainDesc& d,
                                     hipStream_t stream);

@@ -1,420 +1,744 @@
-// Persistent step kernel: one 1024-thread workgroup advances one
+// Persistent step kernel: one 512-thread workgroup advances one
 // decomposition by many SGD steps without leaving the chip.
 //
 // One step (paper Section 3, Algorithms 3-5):
-//   1. mode draw and inverse-CDF sampling of B rows per mode k != n from the
-//      integer-valued CDFs held in LDS (Philox4x64-10 words, Lemmas 2/4);
-//   2. p_f = prod_k q_k(i_k)/Q_k, w_f = 1/(B p_f), fibre row offsets by the
-//      unfolding index map, sampled KRP rows H (Hadamard of factor rows);
-//   3. Gs = H^T W H in FP64, then WH in place;
-//   4. M^T = (WH)^T X_s on the matrix cores (v_mfma_f32_16x16x4f32): every
-//      wave owns a 16-column tile of the I_n x R output and streams the
-//      gathered fibres straight from HBM into the B operand; the fibre dimension
-//      is split across waves when there are fewer than 16 tiles and the partial
-//      tiles are summed in a fixed order;
-//   5. G = A^(n) Gs - M and the fixed / decreasing / AdaGrad update;
-//   6. the CDF of mode n is rebuilt from the new factor (squared row norms or
-//      leverage scores via FP64 Gram + Cholesky), quantised to exact integers.
+//   1. mode draw and inverse-CDF sampling of B rows of every mode k != n
+//      from the integer-valued CDFs held in LDS (Philox4x64-10 words,
+//      Lemmas 2 and 4); one thread per draw.  The Philox words of the next
+//      step are generated ahead by threads that are idle in phase 2.
+//   2. one thread per sampled fibre: p_f = prod_k q_k(i_k)/Q_k,
+//      w_f = 1/(B p_f), the fibre's row in copy n (unfolding index map) and
+//      the sampled KRP row H(f,:) = Hadamard product of factor rows, written
+//      as WH in the A-operand layout of the matrix-core instruction.
+//   3. Gs = (WH)^T H on the matrix cores, the fibre dimension split over
+//      the waves and the partial tiles summed in a fixed order.
+//   4. on the matrix cores (v_mfma_f32_16x16x4f32), per 16-column tile of the
+//      I_n x R output: -G^T = (WH)^T X_s - Gs^T A^(n)T, the fibres streamed
+//      from HBM straight into the B operand with two register buffers; the
+//      tile's lanes then apply the fixed, decreasing or AdaGrad update
+//      (optional projection onto A >= 0) to the entries they hold.
+//   5. the CDF of mode n from the new factor: squared row norms, or leverage
+//      scores from an FP64 Gram, a one-wave Cholesky and a forward solve per
+//      row; quantised to exact integers and prefix-summed.
 #include "cpd_internal.hpp"
 
 namespace cpdmi {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
+extern __shared__ __align__(16) unsigned char cpd_smem[];
 
-// Block-wide maximum (every thread receives it).  scratch: kWaves doubles.
-__device__ double block_max(double v, double* scratch) {
-  v = wave_max(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = scratch[0];
-  for (int i = 1; i < kWaves; ++i) r = fmax(r, scratch[i]);
-  return r;
-}
-
-// In-place inclusive prefix sum of data[0..L) in LDS.  The values are
-// integers below 2^53, so every partial sum is exact and the order of the
-// additions does not matter.  scratch: kWaves doubles.
-__device__ void block_scan(double* data, int L, double* scratch) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double carry = 0.0;
-  for (int base = 0; base < L; base += kBlock) {
-    const int i = base + threadIdx.x;
-    double v = i < L ? data[i] : 0.0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const double u = __shfl_up(v, o);
-      if (lane >= o) v += u;
-    }
-    __syncthreads();
-    if (lane == 63) scratch[w] = v;
-    __syncthreads();
-    double off = carry, tot = carry;
-    for (int j = 0; j < kWaves; ++j) {
-      if (j < w) off += scratch[j];
-      tot += scratch[j];
-    }
-    if (i < L) data[i] = v + off;
-    carry = tot;
-  }
-  __syncthreads();
-}
-
-__device__ inline void pair_of(int pr, int R, int& r, int& s) {
-  int rr = 0;
-  while (pr >= R - rr) {
-    pr -= R - rr;
-    ++rr;
-  }
-  r = rr;
-  s = rr + pr;
-}
-
-// Symmetric Gram-type sum out[r][s] = sum_{e < n} x(e, r) x(e, s) * wt(e), FP64,
-// for the R(R+1)/2 pairs, summed in a fixed order.  `get(e, r)` returns a
-// double; `wt(e)` the weight.  part: >= kBlock doubles.
-template <typename Get, typename Wt>
-__device__ void gram_fixed_order(int n, int R, Get get, Wt wt, double* out, double* part) {
-  const int npairs = R * (R + 1) / 2;
-  if (npairs <= kBlock) {
-    int nch = kBlock / npairs;
-    if (nch > n) nch = n;
-    if (nch < 1) nch = 1;
-    const int pr = threadIdx.x % npairs, ch = threadIdx.x / npairs;
-    if (ch < nch) {
-      int r, s;
-      pair_of(pr, R, r, s);
-      double acc = 0.0;
-      for (int e = ch; e < n; e += nch) acc += wt(e) * (get(e, r) * get(e, s));
-      part[ch * npairs + pr] = acc;
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < npairs; p += kBlock) {
-      int r, s;
-      pair_of(p, R, r, s);
-      double acc = 0.0;
-      for (int c = 0; c < nch; ++c) acc += part[c * npairs + p];
-      out[r * R + s] = acc;
-      out[s * R + r] = acc;
-    }
-  } else {
-    for (int p = threadIdx.x; p < npairs; p += kBlock) {
-      int r, s;
-      pair_of(p, R, r, s);
-      double acc = 0.0;
-      for (int e = 0; e < n; ++e) acc += wt(e) * (get(e, r) * get(e, s));
-      out[r * R + s] = acc;
-      out[s * R + r] = acc;
-    }
-  }
-  __syncthreads();
-}
-
+// Offsets of the LDS regions of one workgroup.  Pointers are always formed
+// from the LDS array itself so the compiler keeps them in the LDS address
+// space (DS instructions) instead of generic pointers.
 struct Smem {
-  double* cdf;
-  int32_t* idx;
-  uint64_t* words;
-  double* wf;
-  int64_t* rowoff;
-  float* hb;
-  double* gs;
-  float* mbuf;
-  double* part;
-  double* wts;
-  int32_t* misc;  // [0] mode, [1] error, [2..] scratch
-  double* red;    // kWaves doubles for reductions
-  int* coff;      // LDS: offset of each mode's CDF
-  int rp16, bpad, ms, nd;
+  uint32_t o_cdf, o_idx, o_ratio, o_words, o_wf, o_rinv, o_rowoff, o_wht, o_gs, o_gsp, o_mbuf,
+      o_gram, o_part, o_red, o_wts, o_misc, o_sbuf;
+  int rp16, bpad, ms, nd, nblk, has_sbuf;
+  __device__ double* cdf() const { return (double*)(cpd_smem + o_cdf); }
+  __device__ int32_t* idx() const { return (int32_t*)(cpd_smem + o_idx); }        // [f][slot]
+  __device__ double* ratio() const { return (double*)(cpd_smem + o_ratio); }      // [slot][f]
+  __device__ uint64_t* words() const { return (uint64_t*)(cpd_smem + o_words); }  // Philox
+  __device__ float* wf() const { return (float*)(cpd_smem + o_wf); }              // w_f
+  __device__ float* rinv() const { return (float*)(cpd_smem + o_rinv); }          // 1 / w_f
+  // byte offset of fibre f in copy n at rowb()[(f >> 4) * 16 + (f & 3) * 4 + ((f >> 2) & 3)]:
+  // the offsets of K-steps 4q..4q+3 for one lane group are one 16-byte read
+  __device__ uint32_t* rowb() const { return (uint32_t*)(cpd_smem + o_rowoff); }
+  __device__ float* wht() const { return (float*)(cpd_smem + o_wht); }            // WH, A layout
+  __device__ float* gs() const { return (float*)(cpd_smem + o_gs); }              // Gs [rp16]^2
+  __device__ float* gsp() const { return (float*)(cpd_smem + o_gsp); }            // Gs partials
+  __device__ float* mbuf() const { return (float*)(cpd_smem + o_mbuf); }          // rows [I_n][ms]
+  __device__ float* sbuf() const { return (float*)(cpd_smem + o_sbuf); }          // S^(n) rows
+  __device__ double* gram() const { return (double*)(cpd_smem + o_gram); }
+  __device__ double* part() const { return (double*)(cpd_smem + o_part); }
+  __device__ double* red() const { return (double*)(cpd_smem + o_red); }
+  __device__ double* wts() const { return (double*)(cpd_smem + o_wts); }
+  __device__ int32_t* misc() const { return (int32_t*)(cpd_smem + o_misc); }
+  __device__ int32_t* coff() const { return misc() + 8; }  // CDF offset of each mode
 };
+// misc(): [1] error, [2] rank flag, [4] next-step Philox blocks generated
 
-// Rebuild the integer-valued CDF of mode n from the factor rows held in
-// mbuf (row i at mbuf[i * ms], R floats).  Returns a cpd_status.
-__device__ int refresh_cdf(const ChainDesc* dp, Smem& S, int n) {
+__device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Waits for this wave's LDS traffic and orders it against later LDS reads
+// of other lanes of the same wave.
+__device__ inline void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); }
+
+// Position of (K-step k, rank tile rt, lane) in the A-operand layout: the
+// four K-steps 4q..4q+3 of one lane are contiguous (one 16-byte LDS read).
+__device__ inline int wht_index(int k, int rt, int lane, int RT) {
+  return ((k >> 2) * RT + rt) * 256 + lane * 4 + (k & 3);
+}
+
+// ---------------------------------------------------------------------------
+// CDF of mode n from the factor rows in mbuf (row i at mbuf[i * ms]).
+// ---------------------------------------------------------------------------
+template <int RT>
+__device__ __forceinline__ int refresh_cdf(const ChainDesc* dp, const Smem& S, int n) {
   const int R = dp->R, In = dp->dims[n];
   const int ms = S.ms;
-  double* w = S.wts;
+  const float* mb = S.mbuf();
+  double* w = S.wts();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int err = 0;
-  if (dp->sampler == CPD_SAMPLER_UNIFORM) {
-    for (int i = threadIdx.x; i < In; i += kBlock) w[i] = 1.0;
-  } else if (dp->sampler == CPD_SAMPLER_EUCLIDEAN) {
-    for (int i = threadIdx.x; i < In; i += kBlock) {
-      double acc = 0.0;
-      for (int r = 0; r < R; ++r) {
-        const double a = (double)S.mbuf[i * ms + r];
-        acc = acc + a * a;  // a*a is exact in FP64 for an FP32 a
-      }
-      w[i] = acc;
-    }
-  } else {
-    // leverage scores: l_i = ||L^{-1} a_i||^2 with L L^T = A^T A (FP64)
-    double* G = S.gs;           // R x R, becomes L (lower triangle)
-    double* Li = S.part;        // R x R, L^{-1} (lower triangle)
-    const float* mb = S.mbuf;
-    gram_fixed_order(
-        In, R, [&](int e, int r) { return (double)mb[e * ms + r]; }, [](int) { return 1.0; }, G,
-        S.part);
-    if (threadIdx.x == 0) S.misc[2] = 0;
-    __syncthreads();
-    for (int j = 0; j < R; ++j) {
-      // every thread reads the same pivot, so the branch below is uniform
-      double d = G[j * R + j];
-      const double diag = d;
-      for (int k = 0; k < j; ++k) d -= G[j * R + k] * G[j * R + k];
-      const bool ok = d > kRankTol * diag && isfinite(d);
-      const double ljj = ok ? sqrt(d) : 1.0;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        G[j * R + j] = ljj;
-        if (!ok) S.misc[2] = 1;
-      }
-      for (int i = j + 1 + (int)threadIdx.x; i < R; i += kBlock) {
-        double v = G[i * R + j];
-        for (int k = 0; k < j; ++k) v -= G[i * R + k] * G[j * R + k];
-        G[i * R + j] = v / ljj;
-      }
-      __syncthreads();
-    }
-    if (S.misc[2]) err = CPD_E_RANK_DEFICIENT;
-    // columns of L^{-1}, one lane per column
-    for (int c = threadIdx.x; c < R; c += kBlock) {
-      for (int j = 0; j < R; ++j) {
-        if (j < c) {
-          Li[j * R + c] = 0.0;
-          continue;
+  if (dp->sampler == CPD_SAMPLER_LEVERAGE) {
+    // leverage scores l_i = ||L^{-1} a_i||^2 with L L^T = A^T A (FP64)
+    double* G = S.gram();
+    const int npairs = R * (R + 1) / 2;
+    if (npairs <= kBlock) {
+      // pairs x row chunks, partials summed in a fixed order
+      int nch = kBlock / npairs;
+      if (nch > In) nch = In;
+      const int pr = threadIdx.x % npairs, ch = threadIdx.x / npairs;
+      if (ch < nch) {
+        int r = 0, rem = pr;
+        while (rem >= R - r) {
+          rem -= R - r;
+          ++r;
         }
-        double v = j == c ? 1.0 : 0.0;
-        for (int k = c; k < j; ++k) v -= G[j * R + k] * Li[k * R + c];
-        Li[j * R + c] = v / G[j * R + j];
+        const int c = r + rem;
+        double acc0 = 0.0, acc1 = 0.0;
+        int i = ch;
+        for (; i + nch < In; i += 2 * nch) {
+          acc0 += (double)mb[i * ms + r] * (double)mb[i * ms + c];
+          acc1 += (double)mb[(i + nch) * ms + r] * (double)mb[(i + nch) * ms + c];
+        }
+        if (i < In) acc0 += (double)mb[i * ms + r] * (double)mb[i * ms + c];
+        S.part()[ch * npairs + pr] = acc0 + acc1;
+      }
+      __syncthreads();
+      for (int p = threadIdx.x; p < npairs; p += kBlock) {
+        int r = 0, rem = p;
+        while (rem >= R - r) {
+          rem -= R - r;
+          ++r;
+        }
+        const int c = r + rem;
+        double acc = 0.0;
+        for (int q = 0; q < nch; ++q) acc += S.part()[q * npairs + p];
+        G[r * R + c] = acc;
+        G[c * R + r] = acc;
+      }
+    } else {
+      for (int p = threadIdx.x; p < npairs; p += kBlock) {
+        int r = 0, rem = p;
+        while (rem >= R - r) {
+          rem -= R - r;
+          ++r;
+        }
+        const int c = r + rem;
+        double acc = 0.0;
+        for (int i = 0; i < In; ++i) acc += (double)mb[i * ms + r] * (double)mb[i * ms + c];
+        G[r * R + c] = acc;
+        G[c * R + r] = acc;
       }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < In; i += kBlock) {
-      double l = 0.0;
+    // Cholesky by one wave (lane = row); the lower triangle of G becomes L
+    if (threadIdx.x < 64) {
+      bool ok = true;
       for (int j = 0; j < R; ++j) {
-        double y = 0.0;
-        for (int k = 0; k <= j; ++k) y += Li[j * R + k] * (double)mb[i * ms + k];
-        l += y * y;
+        double d = G[j * R + j];
+        const double diag = d;
+        for (int k = 0; k < j; ++k) d -= G[j * R + k] * G[j * R + k];
+        const bool okj = d > kRankTol * diag && isfinite(d);
+        ok = ok && okj;
+        const double ljj = okj ? sqrt(d) : 1.0;
+        const double inv = 1.0 / ljj;
+        for (int i = j + 1 + lane; i < R; i += 64) {
+          double v = G[i * R + j];
+          for (int k = 0; k < j; ++k) v -= G[i * R + k] * G[j * R + k];
+          G[i * R + j] = v * inv;
+        }
+        wave_lds_sync();
+        if (lane == 0) G[j * R + j] = ljj;
+        wave_lds_sync();
+      }
+      if (lane == 0 && !ok) S.misc()[2] = 1;
+    }
+    __syncthreads();
+    if (S.misc()[2]) err = CPD_E_RANK_DEFICIENT;
+    // l_i by forward substitution L y = a_i (y in registers)
+    for (int i = threadIdx.x; i < In; i += kBlock) {
+      double y[RT * 16];
+      double l = 0.0;
+#pragma unroll
+      for (int j = 0; j < RT * 16; ++j) {
+        if (j < R) {
+          double v = (double)mb[i * ms + j];
+#pragma unroll
+          for (int k = 0; k < j; ++k) v -= G[j * R + k] * y[k];
+          y[j] = v / G[j * R + j];
+          l += y[j] * y[j];
+        } else {
+          y[j] = 0.0;
+        }
       }
       w[i] = l;
     }
-  }
-  __syncthreads();
-  // quantise: q_i = ceil(w_i 2^E), 2^E * max(w) * 2^ceil(log2 In) < 2^53
-  double lmax = 0.0;
-  bool fin = true;
-  for (int i = threadIdx.x; i < In; i += kBlock) {
-    lmax = fmax(lmax, w[i]);
-    fin = fin && isfinite(w[i]) && w[i] >= 0.0;
-  }
-  if (!fin) S.misc[3] = 1;
-  const double wmax = block_max(lmax, S.red);
-  const bool bad = S.misc[3] != 0;
-  __syncthreads();
-  if (bad || !(wmax > 0.0) || !isfinite(wmax)) {
-    if (threadIdx.x == 0) S.misc[3] = 0;
     __syncthreads();
-    return err ? err : CPD_E_DEGENERATE;
   }
+  // quantise: q_i = ceil(w_i 2^E), 2^E * max(w) * 2^ceil(log2 In) < 2^53,
+  // then the inclusive prefix sum (exact integers, so any order gives the
+  // same bits)
+  double* red = S.red();
+  double* C = S.cdf() + S.coff()[n];
+  CPD_GLOBAL double* Cg = gmem(dp->C[n]);
+  const int c = bit_length_u32((uint32_t)(In - 1));
+  if (In <= kBlock) {
+    const int i = threadIdx.x;
+    double wi = 0.0;
+    if (i < In) {
+      if (dp->sampler == CPD_SAMPLER_EUCLIDEAN) {
+        for (int r = 0; r < R; ++r) {
+          const double a = (double)mb[i * ms + r];
+          wi = wi + a * a;  // a*a is exact in FP64 for an FP32 a
+        }
+      } else if (dp->sampler == CPD_SAMPLER_UNIFORM) {
+        wi = 1.0;
+      } else {
+        wi = w[i];
+      }
+    }
+    const bool fin = i >= In || (isfinite(wi) && wi >= 0.0);
+    double m = fin ? wi : __builtin_inf();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if (lane == 0) red[wave] = m;
+    __syncthreads();
+    double wmax = red[0];
+    for (int j = 1; j < kWaves; ++j) wmax = fmax(wmax, red[j]);
+    if (!(wmax > 0.0) || !isfinite(wmax)) return err ? err : CPD_E_DEGENERATE;
+    int ex;
+    frexp(wmax, &ex);
+    double q = i < In ? ceil(ldexp(wi, 52 - ex - c)) : 0.0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double u = __shfl_up(q, o);
+      if (lane >= o) q += u;
+    }
+    if (lane == 63) red[kWaves + wave] = q;
+    __syncthreads();
+    double off = 0.0;
+    for (int j = 0; j < wave; ++j) off += red[kWaves + j];
+    if (i < In) {
+      C[i] = q + off;
+      Cg[i] = q + off;
+    }
+    return err;
+  }
+  // general path (more rows than threads)
+  if (dp->sampler != CPD_SAMPLER_LEVERAGE) {
+    for (int i = threadIdx.x; i < In; i += kBlock) {
+      double acc = 0.0;
+      if (dp->sampler == CPD_SAMPLER_EUCLIDEAN) {
+        for (int r = 0; r < R; ++r) {
+          const double a = (double)mb[i * ms + r];
+          acc = acc + a * a;
+        }
+      } else {
+        acc = 1.0;
+      }
+      w[i] = acc;
+    }
+  }
+  double m = 0.0;
+  for (int i = threadIdx.x; i < In; i += kBlock)
+    m = fmax(m, (isfinite(w[i]) && w[i] >= 0.0) ? w[i] : __builtin_inf());
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  __syncthreads();
+  if (lane == 0) red[wave] = m;
+  __syncthreads();
+  double wmax = red[0];
+  for (int j = 1; j < kWaves; ++j) wmax = fmax(wmax, red[j]);
+  if (!(wmax > 0.0) || !isfinite(wmax)) return err ? err : CPD_E_DEGENERATE;
   int ex;
   frexp(wmax, &ex);
-  const int c = bit_length_u32((uint32_t)(In - 1));
-  const int E = 52 - ex - c;
-  double* C = S.cdf + S.coff[n];
-  for (int i = threadIdx.x; i < In; i += kBlock) C[i] = ceil(ldexp(w[i], E));
-  __syncthreads();
-  block_scan(C, In, S.red);
-  double* Cg = dp->C[n];
-  for (int i = threadIdx.x; i < In; i += kBlock) Cg[i] = C[i];
-  __syncthreads();
+  double carry = 0.0;
+  for (int base = 0; base < In; base += kBlock) {
+    const int i = base + threadIdx.x;
+    double q = i < In ? ceil(ldexp(w[i], 52 - ex - c)) : 0.0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double u = __shfl_up(q, o);
+      if (lane >= o) q += u;
+    }
+    __syncthreads();
+    if (lane == 63) red[kWaves + wave] = q;
+    __syncthreads();
+    double off = carry, tot = carry;
+    for (int j = 0; j < kWaves; ++j) {
+      if (j < wave) off += red[kWaves + j];
+      tot += red[kWaves + j];
+    }
+    if (i < In) {
+      C[i] = q + off;
+      Cg[i] = q + off;
+    }
+    carry = tot;
+  }
   return err;
 }
 
 // ---------------------------------------------------------------------------
-// The contraction M^T (R x I_n) = (WH)^T (R x B) * X_s (B x I_n) for one
-// column tile, K = fibres [4*k0, 4*k1).  VW consecutive columns per lane
-// (one MFMA per column slot), RT row tiles of 16.
+// Gs = (WH)^T H, 16x16 tiles, the K-steps split over the waves; partial
+// tiles summed in a fixed order.  H = WH / w is recovered in the B operand.
 //   A operand (16 x 4): lane l holds WH[f0 + l/16][rt*16 + l%16]
-//   B operand (4 x 16): lane l holds X_s[f0 + l/16][col + (l%16)*VW + v]
+//   B operand (4 x 16): lane l holds H[f0 + l/16][ct*16 + l%16]
 //   D (16 x 16): lane l, element q holds row 4*(l/16)+q, column l%16
 // ---------------------------------------------------------------------------
-template <int VW, int RT, bool BF16, int U>
-__device__ void contract_tile(f4 (&acc)[RT][VW], const void* __restrict__ Xn,
-                              const int64_t* __restrict__ rowoff, const float* __restrict__ wh,
-                              int rp16, int col0, int k0, int k1) {
-  const int lane = threadIdx.x & 63;
+template <int RT>
+__device__ __forceinline__ void compute_gs(const Smem& S) {
+  const int lane = threadIdx.x & 63, wave = uniform_int(threadIdx.x >> 6);
   const int fl = lane >> 4, cl = lane & 15;
-  const int col = col0 + cl * VW;
+  constexpr int T2 = RT * RT;
+  constexpr int kparts = T2 >= kWaves ? 1 : kWaves / T2;
+  constexpr int items = T2 * kparts;
+  const int nq = S.bpad / 16;  // groups of four K-steps
+  const float* wht = S.wht();
+  const float* rinv = S.rinv();
+  float* gsp = S.gsp();
+  for (int it = wave; it < items; it += kWaves) {
+    const int tile = it % T2, kp = it / T2;
+    const int rt = tile / RT, ct = tile % RT;
+    const int q0 = kp * nq / kparts, q1 = (kp + 1) * nq / kparts;
+    f4 g = f4{0.f, 0.f, 0.f, 0.f};
+    for (int q = q0; q < q1; ++q) {
+      const f4 a4 = *(const f4*)(wht + (q * RT + rt) * 256 + lane * 4);
+      const f4 h4 = *(const f4*)(wht + (q * RT + ct) * 256 + lane * 4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float b = h4[j] * rinv[(4 * q + j) * 4 + fl];
+        g = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[j], b, g, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) gsp[it * 256 + (4 * fl + e) * 16 + cl] = g[e];
+  }
+  __syncthreads();
+  const int rp16 = S.rp16;
+  for (int e = threadIdx.x; e < rp16 * rp16; e += kBlock) {
+    const int r = e / rp16, s2 = e - r * rp16;
+    const int tile = (r >> 4) * RT + (s2 >> 4);
+    float acc = 0.f;
+    for (int kp = 0; kp < kparts; ++kp)
+      acc += gsp[(kp * T2 + tile) * 256 + (r & 15) * 16 + (s2 & 15)];
+    S.gs()[e] = acc;
+  }
+  __syncthreads();
+}
+
+// A^(n) into mbuf (row i at mbuf[i * ms]) for the contraction epilogue, in
+// two halves so the loads can be in flight while the draws are searched:
+// prefetch_issue loads the first 8 * kBlock entries into registers,
+// prefetch_commit stores them (and any further rows) and zeroes the rank
+// padding columns.
+constexpr int kPrefetch = 4;
+__device__ __forceinline__ void prefetch_issue(const ChainDesc* dp, const Smem& S, int n,
+                                               float (&v)[kPrefetch], float (&sv)[kPrefetch]) {
+  const int total = dp->dims[n] * dp->R;
+  const CPD_GLOBAL float* An = gmem(dp->A[n]);
+  const CPD_GLOBAL float* Sn = gmem(dp->S[n]);
+  const bool ss = S.has_sbuf && dp->rule == CPD_RULE_ADAGRAD;
+#pragma unroll
+  for (int j = 0; j < kPrefetch; ++j) {
+    const int e = threadIdx.x + j * kBlock;
+    v[j] = e < total ? An[e] : 0.f;
+    sv[j] = (ss && e < total) ? Sn[e] : 0.f;
+  }
+}
+
+__device__ __forceinline__ void prefetch_commit(const ChainDesc* dp, const Smem& S, int n,
+                                                const float (&v)[kPrefetch],
+                                                const float (&sv)[kPrefetch]) {
+  const int R = dp->R, In = dp->dims[n], total = In * R, ms = S.ms;
+  float* mbuf = S.mbuf();
+  float* sbuf = S.sbuf();
+  const bool ss = S.has_sbuf && dp->rule == CPD_RULE_ADAGRAD;
+#pragma unroll
+  for (int j = 0; j < kPrefetch; ++j) {
+    const int e = threadIdx.x + j * kBlock;
+    if (e < total) {
+      const int i = e / R;
+      mbuf[i * ms + (e - i * R)] = v[j];
+      if (ss) sbuf[i * ms + (e - i * R)] = sv[j];
+    }
+  }
+  const CPD_GLOBAL float* An = gmem(dp->A[n]);
+  const CPD_GLOBAL float* Sn = gmem(dp->S[n]);
+  for (int e = threadIdx.x + kPrefetch * kBlock; e < total; e += kBlock) {
+    const int i = e / R;
+    mbuf[i * ms + (e - i * R)] = An[e];
+    if (ss) sbuf[i * ms + (e - i * R)] = Sn[e];
+  }
+  const int padc = ms - R;
+  for (int e = threadIdx.x; e < In * padc; e += kBlock) {
+    const int i = e / padc;
+    mbuf[i * ms + R + (e - i * padc)] = 0.f;
+  }
+}
+
+// The update of one entry: returns the new value, updates the accumulator.
+__device__ __forceinline__ float update_entry(const ChainDesc* dp, float a, float g, float& sacc,
+                                              float alpha_t) {
+  float an;
+  if (dp->rule == CPD_RULE_ADAGRAD) {
+    sacc = sacc + g * g;
+    const float den = sqrtf(dp->b + sacc);
+    an = den > 0.f ? a - dp->eta * g / den : a;
+  } else {
+    an = a - alpha_t * g;
+  }
+  if (dp->nonneg) an = fmaxf(an, 0.f);
+  return an;
+}
+
+// ---------------------------------------------------------------------------
+// Contraction and update for mode n.  Per 16-column tile (columns col0 +
+// j*VW + v of the I_n x R output), K = padded fibres:
+//   A operand: lane l holds WH[f0 + l/16][rt*16 + l%16]   (LDS)
+//   B operand: lane l holds X_s[f0 + l/16][col0 + (l%16)*VW + v]   (HBM)
+// followed by K = rank (steps of 4) with A = -Gs[rt*16 + l%16][s0 + l/16]
+// and B = A^(n)[col0 + (l%16)*VW + v][s0 + l/16], which leaves -G^T in the
+// accumulators.  A wave walks all K-chunks of all its tiles as one stream
+// with two register buffers.
+// ---------------------------------------------------------------------------
+template <int VW, int RT, bool BF16>
+__device__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint64_t t) {
+  constexpr int U = kChunkSteps / VW / RT;  // K-steps per part of the fibre range
+  const int lane = threadIdx.x & 63;
+  const int wave = uniform_int(threadIdx.x >> 6);
+  const int fl = lane >> 4, cl = lane & 15;
+  const int In = dp->dims[n], R = dp->R, ms = S.ms, rp16 = S.rp16;
+  const int SW = 16 * VW;
+  const int nst = (In + SW - 1) / SW;
+  const int ks = dp->ksplit[n];
+  const int nck_all = S.bpad / (4 * U);  // bpad is a multiple of 4 * kChunkSteps
+  const float* __restrict__ wht = S.wht();
+  const uint32_t* __restrict__ rowb = S.rowb();
+  const CPD_GLOBAL char* __restrict__ Xb = gmem((const char*)dp->X[n]);
+  CPD_GLOBAL float* An = gmem(dp->A[n]);
+  CPD_GLOBAL float* Sn = gmem(dp->S[n]);
+  const bool ada = dp->rule == CPD_RULE_ADAGRAD;
+  const float alpha_t = dp->rule == CPD_RULE_DECREASING
+                            ? (float)(dp->beta / ((double)t + dp->gamma))
+                            : dp->alpha;
+  float* mbuf = S.mbuf();
+
+  int nitems, c0, c1, st_first, kc = 0;
+  if (ks <= 1) {
+    nitems = wave < nst ? (nst - 1 - wave) / kWaves + 1 : 0;
+    c0 = 0;
+    c1 = nck_all;
+    st_first = wave;
+  } else {
+    kc = wave / nst;
+    nitems = wave < nst * ks ? 1 : 0;
+    c0 = kc * nck_all / ks;
+    c1 = (kc + 1) * nck_all / ks;
+    st_first = wave % nst;
+  }
+  const int nck = c1 - c0;
+  // the tile's lanes update their entries directly when the whole fibre
+  // range is theirs and the AdaGrad accumulators are staged in LDS;
+  // otherwise -G^T goes to mbuf and an element-wise pass updates
+  const bool direct = ks <= 1 && S.has_sbuf;
+  bool bad = false;
+
+  f4 acc[RT][VW];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int v = 0; v < VW; ++v) acc[rt][v] = f4{0.f, 0.f, 0.f, 0.f};
-
-  // two register buffers with compile-time indices (a runtime-indexed
-  // private array would live in scratch memory)
-  float xa[U][VW], xb[U][VW];
-  auto load = [&](float (&x)[U][VW], int kbase) {
+  // -Gs^T A^T added to the accumulators of tile st
+  auto add_ags = [&](int st) {
+    const int col0 = st * SW;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int ks = kbase + u;
-      if (ks < k1) {
-        const int f = ks * 4 + fl;
-        const int64_t off = rowoff[f] + col;
-        if constexpr (BF16) {
-          const uint32_t pk = *(const uint32_t*)((const uint16_t*)Xn + off);
-          x[u][0] = __uint_as_float(pk << 16);
-          if constexpr (VW > 1) x[u][1] = __uint_as_float(pk & 0xFFFF0000u);
-        } else {
-          const float* p = (const float*)Xn + off;
+    for (int kk = 0; kk < 4 * RT; ++kk) {
+      const int s = 4 * kk + fl;
+      float bA[VW];
 #pragma unroll
-          for (int v = 0; v < VW; ++v) x[u][v] = p[v];
-        }
-      } else {
+      for (int v = 0; v < VW; ++v) {
+        // rows past I_n only feed output columns that are never stored;
+        // rank columns past R are zero in the prefetched rows
+        const int i = col0 + cl * VW + v;
+        bA[v] = mbuf[(i < In ? i : In - 1) * ms + s];
+      }
 #pragma unroll
-        for (int v = 0; v < VW; ++v) x[u][v] = 0.f;
+      for (int rt = 0; rt < RT; ++rt) {
+        const float a = -S.gs()[(rt * 16 + cl) * rp16 + s];
+#pragma unroll
+        for (int v = 0; v < VW; ++v)
+          acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bA[v], acc[rt][v], 0, 0, 0);
       }
     }
   };
-  auto compute = [&](const float (&x)[U][VW], int kbase) {
+  // AdaGrad accumulators of the entries this lane will update, loaded when
+  // the tile starts so the load latency hides behind the tile's chunks
+  float sv[RT][VW][4];
+  auto load_s = [&](int st) {
+    const int col0 = st * SW;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int ks = kbase + u;
-      if (ks < k1) {
-        const int f = ks * 4 + fl;
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          const float a = wh[f * rp16 + rt * 16 + cl];
+      for (int v = 0; v < VW; ++v)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = rt * 16 + 4 * fl + q;
+          const int i = col0 + cl * VW + v;
+          const bool in = ada && r < R && i < In;
+          sv[rt][v][q] = in ? S.sbuf()[i * ms + r] : 0.f;
+        }
+  };
+  // -G^T of tile st into mbuf (the tile's rows were only read by this wave)
+  auto store_neg_g = [&](int st) {
+    const int col0 = st * SW;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < VW; ++v)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = rt * 16 + 4 * fl + q;
+          const int i = col0 + cl * VW + v;
+          if (r < R && i < In) mbuf[i * ms + r] = acc[rt][v][q];
+        }
+  };
+  // the update of the entries of tile st that this lane holds
+  auto update_tile = [&](int st) {
+    const int col0 = st * SW;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < VW; ++v)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = rt * 16 + 4 * fl + q;
+          const int i = col0 + cl * VW + v;
+          if (r < R && i < In) {
+            // LDS only: a global store here would queue behind the fibre
+            // loads in flight; the rows are written back after the phase
+            const float g = -acc[rt][v][q];
+            float sacc = sv[rt][v][q];
+            const float an = update_entry(dp, mbuf[i * ms + r], g, sacc, alpha_t);
+            if (ada) S.sbuf()[i * ms + r] = sacc;
+            if (!isfinite(an)) bad = true;
+            mbuf[i * ms + r] = an;
+          }
+        }
+  };
+  // The wave's work is a stream of chunks (U K-steps each) over its items;
+  // two register buffers: the loads of chunk c+1 are in flight while chunk
+  // c is multiplied.  Two accumulator sets (even / odd K-steps) halve the
+  // dependent-accumulation chain.
+  f4 acc2[RT][VW];
+  float xa[U][VW], xb[U][VW];
+  auto load = [&](float (&x)[U][VW], int c) {
+    const int it = c / nck;
+    const int st = st_first + it * kWaves;
+    const int kq0 = (c0 + (c - it * nck)) * (U / 4);  // first group of 4 K-steps
+    const uint32_t colb = (uint32_t)((st * SW + cl * VW) * (BF16 ? 2 : 4));
+    if (direct && c - it * nck == 0) load_s(st);
+#pragma unroll
+    for (int u4 = 0; u4 < U / 4; ++u4) {
+      const uint4 ob = *(const uint4*)(rowb + (kq0 + u4) * 16 + fl * 4);
+      const uint32_t o4[4] = {ob.x, ob.y, ob.z, ob.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const CPD_GLOBAL char* p = Xb + (o4[j] + colb);
+        const int u = 4 * u4 + j;
+        if constexpr (BF16) {
+          if constexpr (VW == 2) {
+            const uint32_t pk = *(const CPD_GLOBAL uint32_t*)p;
+            x[u][0] = __uint_as_float(pk << 16);
+            x[u][1] = __uint_as_float(pk & 0xFFFF0000u);
+          } else {
+            x[u][0] = bf16_to_f32(*(const CPD_GLOBAL uint16_t*)p);
+          }
+        } else {
+          if constexpr (VW == 2) {
+            const uint64_t v2 = *(const CPD_GLOBAL uint64_t*)p;
+            x[u][0] = __uint_as_float((uint32_t)v2);
+            x[u][1] = __uint_as_float((uint32_t)(v2 >> 32));
+          } else {
+            x[u][0] = *(const CPD_GLOBAL float*)p;
+          }
+        }
+      }
+    }
+  };
+  auto compute = [&](const float (&x)[U][VW], int c) {
+    const int it = c / nck;
+    const int ci = c - it * nck;
+    const int st = st_first + it * kWaves;
+    const int kq0 = (c0 + ci) * (U / 4);
+    if (ci == 0) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+          acc[rt][v] = f4{0.f, 0.f, 0.f, 0.f};
+          acc2[rt][v] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+#pragma unroll
+    for (int u4 = 0; u4 < U / 4; ++u4) {
+      f4 a4[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) a4[rt] = *(const f4*)(wht + ((kq0 + u4) * RT + rt) * 256 + lane * 4);
+#pragma unroll
+      for (int j = 0; j < 4; j += 2)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int v = 0; v < VW; ++v) {
+            acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[rt][j], x[4 * u4 + j][v],
+                                                              acc[rt][v], 0, 0, 0);
+            acc2[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[rt][j + 1], x[4 * u4 + j + 1][v],
+                                                               acc2[rt][v], 0, 0, 0);
+          }
+    }
+    if (ci == nck - 1) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[rt][v] += acc2[rt][v];
+      if (ks <= 1) {
+        add_ags(st);
+        if (direct) update_tile(st);
+        else store_neg_g(st);
+      }
+    }
+  };
+  const int total = nitems * nck;
+  if (total > 0) {
+    load(xa, 0);
+    for (int c = 0; c < total; c += 2) {
+      if (c + 1 < total) load(xb, c + 1);
+      compute(xa, c);
+      if (c + 2 < total) load(xa, c + 2);
+      if (c + 1 < total) compute(xb, c + 1);
+    }
+  }
+  if (ks > 1) {
+    // K-split: the first part adds -Gs^T A^T, the partial tiles are summed
+    // in a fixed order (one part per round)
+    if (nitems && kc == 0) add_ags(st_first);
+    __syncthreads();  // every add_ags read of the prefetched rows is done
+    for (int round = 0; round < ks; ++round) {
+      if (nitems && kc == round) {
+        const int col0 = st_first * SW;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
           for (int v = 0; v < VW; ++v)
-            acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x[u][v], acc[rt][v], 0, 0, 0);
-        }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int r = rt * 16 + 4 * fl + q;
+              const int i = col0 + cl * VW + v;
+              if (r < R && i < In) {
+                float* m = mbuf + i * ms + r;
+                *m = round ? *m + acc[rt][v][q] : acc[rt][v][q];
+              }
+            }
       }
-    }
-  };
-  if (k0 >= k1) return;
-  load(xa, k0);
-  for (int kb = k0; kb < k1; kb += 2 * U) {
-    if (kb + U < k1) load(xb, kb + U);
-    compute(xa, kb);
-    if (kb + 2 * U < k1) load(xa, kb + 2 * U);
-    if (kb + U < k1) compute(xb, kb + U);
-  }
-}
-
-template <int VW, int RT>
-__device__ void store_tile(const f4 (&acc)[RT][VW], float* mbuf, int ms, int R, int In, int col0,
-                           bool add) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int v = 0; v < VW; ++v)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = rt * 16 + 4 * (lane >> 4) + q;
-        const int i = col0 + (lane & 15) * VW + v;
-        if (r < R && i < In) {
-          float* m = mbuf + i * ms + r;
-          *m = add ? *m + acc[rt][v][q] : acc[rt][v][q];
-        }
-      }
-}
-
-template <int VW, int RT, bool BF16>
-__device__ void contraction(const ChainDesc* dp, Smem& S, int n) {
-  constexpr int U = (VW * RT <= 2) ? 16 : 8;
-  const int In = dp->dims[n];
-  const int SW = 16 * VW;
-  const int nst = (In + SW - 1) / SW;
-  const int ks = dp->ksplit[n];
-  const int KS = S.bpad / 4;
-  const int wave = threadIdx.x >> 6;
-  f4 acc[RT][VW];
-  if (ks <= 1) {
-    for (int st = wave; st < nst; st += kWaves) {
-      contract_tile<VW, RT, BF16, U>(acc, dp->X[n], S.rowoff, S.hb, S.rp16, st * SW, 0, KS);
-      store_tile<VW, RT>(acc, S.mbuf, S.ms, dp->R, In, st * SW, false);
-    }
-    __syncthreads();
-  } else {
-    const bool has = wave < nst * ks;
-    const int st = wave % nst, kc = wave / nst;
-    if (has) {
-      const int k0 = (int)((int64_t)kc * KS / ks), k1 = (int)((int64_t)(kc + 1) * KS / ks);
-      contract_tile<VW, RT, BF16, U>(acc, dp->X[n], S.rowoff, S.hb, S.rp16, st * SW, k0, k1);
-    }
-    for (int round = 0; round < ks; ++round) {
-      if (has && kc == round) store_tile<VW, RT>(acc, S.mbuf, S.ms, dp->R, In, st * SW, round > 0);
       __syncthreads();
     }
+  } else if (!direct) {
+    __syncthreads();
   }
+  if (direct) {
+    // write the updated rows (and accumulators) back, coalesced
+    __syncthreads();
+    for (int e = threadIdx.x; e < In * R; e += kBlock) {
+      const int i = e / R, r = e - i * R;
+      An[e] = mbuf[i * ms + r];
+      if (ada) Sn[e] = S.sbuf()[i * ms + r];
+    }
+  } else {
+    // element-wise update from -G^T in mbuf
+    for (int e = threadIdx.x; e < In * R; e += kBlock) {
+      const int i = e / R, r = e - i * R;
+      const float g = -mbuf[i * ms + r];
+      float sacc = ada ? Sn[e] : 0.f;
+      const float an = update_entry(dp, An[e], g, sacc, alpha_t);
+      if (ada) Sn[e] = sacc;
+      if (!isfinite(an)) bad = true;
+      An[e] = an;
+      mbuf[i * ms + r] = an;
+    }
+  }
+  return bad;
 }
 
-template <int VW, bool BF16>
-__device__ void contraction_rt(const ChainDesc* dp, Smem& S, int n) {
-  switch (dp->RT) {
-    case 1: contraction<VW, 1, BF16>(dp, S, n); break;
-    case 2: contraction<VW, 2, BF16>(dp, S, n); break;
-    case 3: contraction<VW, 3, BF16>(dp, S, n); break;
-    default: contraction<VW, 4, BF16>(dp, S, n); break;
-  }
+// first i in [0, Ik) with C[i] > tg (C ascending, C[Ik-1] > tg)
+__device__ inline int cdf_search(const double* C, int Ik, double tg) {
+  int pos = 0;
+  for (int len = 1 << (31 - __clz(Ik)); len > 0; len >>= 1)
+    if (pos + len <= Ik && C[pos + len - 1] <= tg) pos += len;
+  return pos < Ik ? pos : Ik - 1;
 }
 
+// RT: number of 16-row rank tiles the kernel is compiled for; a chain with
+// fewer tiles runs with zero-padded rank columns.
+template <int RT>
 __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restrict__ descs,
                                                        StepArgs args) {
-  extern __shared__ __align__(16) unsigned char smem[];
   const ChainDesc* dp = descs + blockIdx.x;
   if (!dp->active) return;
   ChainState* st = dp->state;
   if (args.op != OP_SAMPLE && args.op != OP_REFRESH && st->status != 0) return;
   const int tid = threadIdx.x;
   const int N = dp->N, R = dp->R, B = dp->B;
-  const LdsPlan P = lds_plan(N, dp->dims, R, B);
+  const LdsPlan P = lds_plan(N, dp->dims, R, B, RT);
   Smem S;
-  S.cdf = (double*)(smem + P.cdf);
-  S.idx = (int32_t*)(smem + P.idx);
-  S.words = (uint64_t*)(smem + P.words);
-  S.wf = (double*)(smem + P.wf);
-  S.rowoff = (int64_t*)(smem + P.rowoff);
-  S.hb = (float*)(smem + P.hb);
-  S.gs = (double*)(smem + P.gs);
-  S.mbuf = (float*)(smem + P.mbuf);
-  S.part = (double*)(smem + P.part);
-  S.wts = (double*)(smem + P.wts);
-  S.misc = (int32_t*)(smem + P.misc);
-  S.red = (double*)(smem + P.red);
+  S.o_cdf = P.cdf;
+  S.o_idx = P.idx;
+  S.o_ratio = P.ratio;
+  S.o_words = P.words;
+  S.o_wf = P.wf;
+  S.o_rinv = P.rinv;
+  S.o_rowoff = P.rowoff;
+  S.o_wht = P.wht;
+  S.o_gs = P.gs;
+  S.o_gsp = P.gsp;
+  S.o_mbuf = P.mbuf;
+  S.o_gram = P.gram;
+  S.o_part = P.part;
+  S.o_red = P.red;
+  S.o_wts = P.wts;
+  S.o_misc = P.misc;
+  S.o_sbuf = P.sbuf;
+  S.has_sbuf = P.has_sbuf;
   S.rp16 = P.rp16;
   S.bpad = P.bpad;
   S.ms = P.ms;
   S.nd = P.nd;
-  S.coff = S.misc + 8;
-  if (tid < 8) S.misc[tid] = 0;
+  S.nblk = P.nblk;
+  if (tid < 8) S.misc()[tid] = 0;
   if (tid == 0) {
     int o = 0;
     for (int k = 0; k < N; ++k) {
-      S.coff[k] = o;
+      S.coff()[k] = o;
       o += dp->dims[k];
     }
   }
   __syncthreads();
   for (int k = 0; k < N; ++k)
-    for (int i = tid; i < dp->dims[k]; i += kBlock) S.cdf[S.coff[k] + i] = dp->C[k][i];
-  __syncthreads();
+    for (int i = tid; i < dp->dims[k]; i += kBlock) S.cdf()[S.coff()[k] + i] = gmem(dp->C[k])[i];
 
   if (args.op == OP_REFRESH) {
+    __syncthreads();
     int err = 0;
     for (int n = 0; n < N && !err; ++n) {
       for (int e = tid; e < dp->dims[n] * R; e += kBlock) {
         const int i = e / R, r = e - i * R;
-        S.mbuf[i * S.ms + r] = dp->A[n][e];
+        S.mbuf()[i * S.ms + r] = gmem(dp->A[n])[e];
       }
       __syncthreads();
-      err = refresh_cdf(dp, S, n);
+      err = refresh_cdf<RT>(dp, S, n);
+      __syncthreads();
     }
     if (tid == 0 && err) st->status = err;
     return;
@@ -425,170 +749,171 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
   if (args.op == OP_STEP && dp->step_limit > 0 && t0 + nsteps > dp->step_limit)
     nsteps = dp->step_limit > t0 ? dp->step_limit - t0 : 0;
   const int nm1 = N - 1;
-  const int nd = S.nd;
+  const int nd = S.nd, nblk = S.nblk;
+  // threads with no fibre in phase 2 generate the next step's Philox blocks
+  const int npre_max = kBlock > S.bpad ? (kBlock - S.bpad < nblk ? kBlock - S.bpad : nblk) : 0;
+  uint64_t* words = S.words();
   int64_t done = 0;
   int err = 0;
 
   for (int64_t s = 0; s < nsteps; ++s) {
     const uint64_t t = (uint64_t)(t0 + s);
-    // ---- 1. draws -------------------------------------------------------
+    // ---- 1. draws ------------------------------------------------------
+    int n;
     if (args.op == OP_REPLAY) {
+      n = args.replay_mode;
+      float pv[kPrefetch], ps[kPrefetch];
+      prefetch_issue(dp, S, n, pv, ps);
+      prefetch_commit(dp, S, n, pv, ps);
       // caller-supplied indices: reject any outside its mode's range
       for (int e = tid; e < B * nm1; e += kBlock) {
-        const int sl = e % nm1;
-        const int k = sl < args.replay_mode ? sl : sl + 1;
-        const int i = args.replay_idx[e];
-        if (i < 0 || i >= dp->dims[k]) S.misc[1] = CPD_E_INVALID;
-        S.idx[e] = i < 0 ? 0 : (i >= dp->dims[k] ? dp->dims[k] - 1 : i);
+        const int f = e / nm1, sl = e - f * nm1;
+        const int k = sl < n ? sl : sl + 1;
+        int i = gmem(args.replay_idx)[e];
+        if (i < 0 || i >= dp->dims[k]) {
+          S.misc()[1] = CPD_E_INVALID;
+          i = 0;
+        }
+        S.idx()[e] = i;
+        const double* Ck = S.cdf() + S.coff()[k];
+        const double Q = Ck[dp->dims[k] - 1];
+        S.ratio()[sl * B + f] = (Ck[i] - (i ? Ck[i - 1] : 0.0)) / Q;
       }
     } else {
-      const int nblk = (nd + 3) / 4;
-      for (int b = tid; b < nblk; b += kBlock) {
-        uint64_t o[4];
-        philox4x64_10(t, (uint64_t)b, 0, 0, dp->key0, dp->key1, o);
-        S.words[4 * b + 0] = o[0];
-        S.words[4 * b + 1] = o[1];
-        S.words[4 * b + 2] = o[2];
-        S.words[4 * b + 3] = o[3];
+      const int npre = S.misc()[4];
+      if (npre < nblk) {
+        for (int b = npre + tid; b < nblk; b += kBlock) {
+          uint64_t o[4];
+          philox4x64_10(t, (uint64_t)b, 0, 0, dp->key0, dp->key1, o);
+          words[4 * b + 0] = o[0];
+          words[4 * b + 1] = o[1];
+          words[4 * b + 2] = o[2];
+          words[4 * b + 3] = o[3];
+        }
+        __syncthreads();
       }
+      n = (int)mulhi_u64(words[0], (uint64_t)N);
+      float pv[kPrefetch], ps[kPrefetch];
+      prefetch_issue(dp, S, n, pv, ps);
+      for (int d = 1 + tid; d < nd; d += kBlock) {
+        const int sl = (d - 1) / B, f = (d - 1) - sl * B;
+        const int k = sl < n ? sl : sl + 1;
+        const double* Ck = S.cdf() + S.coff()[k];
+        const int Ik = dp->dims[k];
+        const double Q = Ck[Ik - 1];
+        const int i = cdf_search(Ck, Ik, (double)mulhi_u64(words[d], (uint64_t)Q));
+        S.idx()[f * nm1 + sl] = i;
+        S.ratio()[sl * B + f] = (Ck[i] - (i ? Ck[i - 1] : 0.0)) / Q;
+      }
+      prefetch_commit(dp, S, n, pv, ps);
     }
     __syncthreads();
-    if (S.misc[1]) {
-      err = S.misc[1];
+    if (S.misc()[1]) {
+      err = S.misc()[1];
       break;
     }
-    const int n = args.op == OP_REPLAY ? args.replay_mode : (int)mulhi_u64(S.words[0], (uint64_t)N);
-    double* ratio = (double*)S.words;
-    for (int d = 1 + tid; d < nd; d += kBlock) {
-      const int sl = (d - 1) / B, f = (d - 1) - sl * B;
-      const int k = sl < n ? sl : sl + 1;
-      const double* Ck = S.cdf + S.coff[k];
-      const int Ik = dp->dims[k];
-      const double Q = Ck[Ik - 1];
-      int i;
-      if (args.op == OP_REPLAY) {
-        i = S.idx[f * nm1 + sl];
-      } else {
-        const double tg = (double)mulhi_u64(S.words[d], (uint64_t)Q);
-        int lo = 0, hi = Ik - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (Ck[mid] > tg) hi = mid;
-          else lo = mid + 1;
-        }
-        i = lo;
-        S.idx[f * nm1 + sl] = i;
-      }
-      const double q = Ck[i] - (i ? Ck[i - 1] : 0.0);
-      ratio[d] = q / Q;
-    }
-    __syncthreads();
-    // ---- 2. probabilities, weights, fibre rows, KRP rows ----------------
+    if (tid == 0) S.misc()[4] = 0;
+    // ---- 2. one thread per fibre: p_f, w_f, row offset, WH row ----------
     const int ldn = dp->ld[n];
+    const int64_t esz = dp->dtype == CPD_BF16 ? 2 : 4;
+    float* wht = S.wht();
     for (int f = tid; f < S.bpad; f += kBlock) {
+      const int k4 = f >> 2, g4 = f & 3;
       if (f < B) {
         double p = 1.0;
         int64_t j = 0, stride = 1;
         int sl = 0;
         for (int k = 0; k < N; ++k) {
           if (k == n) continue;
-          p = p * ratio[1 + sl * B + f];
-          j += (int64_t)S.idx[f * nm1 + sl] * stride;
+          p = p * S.ratio()[sl * B + f];
+          j += (int64_t)S.idx()[f * nm1 + sl] * stride;
           stride *= dp->dims[k];
           ++sl;
         }
-        S.wf[f] = 1.0 / ((double)B * p);
-        S.rowoff[f] = j * ldn;
+        const float wfl = (float)(1.0 / ((double)B * p));
+        S.wf()[f] = wfl;
+        S.rinv()[f] = (float)((double)B * p);
+        S.rowb()[(f >> 4) * 16 + (f & 3) * 4 + ((f >> 2) & 3)] = (uint32_t)(j * ldn * esz);
         if (args.op == OP_SAMPLE) {
-          args.out_p[f] = p;
-          for (int q = 0; q < nm1; ++q) args.out_idx[f * nm1 + q] = S.idx[f * nm1 + q];
+          gmem(args.out_p)[f] = p;
+          for (int q = 0; q < nm1; ++q) gmem(args.out_idx)[f * nm1 + q] = S.idx()[f * nm1 + q];
+        }
+        // sampled KRP row: product over k != n (ascending) of A^(k)(i_k, :),
+        // 16 columns at a time, the loads of up to three rows issued together
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const int r0 = rt * 16;
+          float h[16];
+          for (int q0 = 0; q0 < nm1; q0 += 3) {
+            float v[3][16];
+#pragma unroll
+            for (int qq = 0; qq < 3; ++qq) {
+              const int q = q0 + qq;
+              if (q < nm1) {
+                const int k = q < n ? q : q + 1;
+                const CPD_GLOBAL float* row = gmem(dp->A[k]) + (int64_t)S.idx()[f * nm1 + q] * R;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) v[qq][c] = r0 + c < R ? row[r0 + c] : 0.f;
+              } else {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) v[qq][c] = 1.f;
+              }
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+              const float prod = (v[0][c] * v[1][c]) * v[2][c];
+              h[c] = q0 == 0 ? prod : h[c] * prod;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 16; ++c) wht[wht_index(k4, rt, g4 * 16 + c, RT)] = wfl * h[c];
         }
       } else {
-        S.wf[f] = 0.0;
-        S.rowoff[f] = 0;
+        S.wf()[f] = 0.f;
+        S.rinv()[f] = 0.f;
+        S.rowb()[(f >> 4) * 16 + (f & 3) * 4 + ((f >> 2) & 3)] = 0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int c = 0; c < 16; ++c) wht[wht_index(k4, rt, g4 * 16 + c, RT)] = 0.f;
       }
     }
     if (args.op == OP_SAMPLE) {
-      if (tid == 0) *args.out_mode = n;
+      if (tid == 0) *gmem(args.out_mode) = n;
       return;
     }
-    for (int e = tid; e < S.bpad * S.rp16; e += kBlock) {
-      const int f = e / S.rp16, r = e - f * S.rp16;
-      float h = 0.f;
-      if (f < B && r < R) {
-        int sl = 0;
-        bool first = true;
-        for (int k = 0; k < N; ++k) {
-          if (k == n) continue;
-          const float a = dp->A[k][(int64_t)S.idx[f * nm1 + sl] * R + r];
-          h = first ? a : h * a;
-          first = false;
-          ++sl;
-        }
-      }
-      S.hb[e] = h;
+    if (args.op == OP_STEP && npre_max > 0 && s + 1 < nsteps && tid >= S.bpad &&
+        tid - S.bpad < npre_max) {
+      // this step's words are consumed; generate the next step's
+      const int b = tid - S.bpad;
+      uint64_t o[4];
+      philox4x64_10(t + 1, (uint64_t)b, 0, 0, dp->key0, dp->key1, o);
+      words[4 * b + 0] = o[0];
+      words[4 * b + 1] = o[1];
+      words[4 * b + 2] = o[2];
+      words[4 * b + 3] = o[3];
+      if (b == 0) S.misc()[4] = npre_max;
     }
     __syncthreads();
-    // ---- 3. Gs = H^T W H (FP64), then WH in place ------------------------
-    {
-      const float* hb = S.hb;
-      const double* wf = S.wf;
-      const int rp = S.rp16;
-      gram_fixed_order(
-          B, R, [&](int f, int r) { return (double)hb[f * rp + r]; },
-          [&](int f) { return wf[f]; }, S.gs, S.part);
-    }
-    for (int e = tid; e < S.bpad * S.rp16; e += kBlock) {
-      const int f = e / S.rp16;
-      S.hb[e] = (float)(S.wf[f] * (double)S.hb[e]);
-    }
+    // ---- 3. Gs ----------------------------------------------------------
+    compute_gs<RT>(S);
+    // ---- 4. contraction and update -----------------------------------------
+    bool bad;
+    if (dp->dtype == CPD_BF16) bad = contract_update<2, RT, true>(dp, S, n, t);
+    else bad = contract_update<1, RT, false>(dp, S, n, t);
+    if (bad) S.misc()[1] = CPD_E_DIVERGED;
     __syncthreads();
-    // ---- 4. M^T = (WH)^T X_s on the matrix cores -------------------------
-    if (dp->dtype == CPD_BF16) contraction_rt<2, true>(dp, S, n);
-    else contraction_rt<1, false>(dp, S, n);
-    // ---- 5. G = A Gs - M and the update -----------------------------------
-    const int In = dp->dims[n];
-    float* An = dp->A[n];
-    float* Sn = dp->S[n];
-    const double alpha_t =
-        dp->rule == CPD_RULE_DECREASING ? dp->beta / ((double)t + dp->gamma) : (double)dp->alpha;
-    bool bad = false;
-    for (int e = tid; e < In * R; e += kBlock) {
-      const int i = e / R, r = e - i * R;
-      const float* arow = An + (int64_t)i * R;
-      double ag = 0.0;
-      for (int q = 0; q < R; ++q) ag += (double)arow[q] * S.gs[q * R + r];
-      const float g = (float)(ag - (double)S.mbuf[i * S.ms + r]);
-      const float a = arow[r];
-      float an;
-      if (dp->rule == CPD_RULE_ADAGRAD) {
-        const float acc = Sn[e] + g * g;
-        Sn[e] = acc;
-        const float den = sqrtf(dp->b + acc);
-        an = den > 0.f ? a - dp->eta * g / den : a;
-      } else {
-        an = a - (float)alpha_t * g;
-      }
-      if (dp->nonneg) an = fmaxf(an, 0.f);
-      if (!isfinite(an)) bad = true;
-      S.mbuf[i * S.ms + r] = an;
-    }
-    if (bad) S.misc[1] = CPD_E_DIVERGED;
-    __syncthreads();
-    for (int e = tid; e < In * R; e += kBlock) {
-      const int i = e / R, r = e - i * R;
-      An[e] = S.mbuf[i * S.ms + r];
-    }
     ++done;
-    if (S.misc[1]) {
-      err = S.misc[1];
+    if (S.misc()[1]) {
+      err = S.misc()[1];
       break;
     }
-    // ---- 6. distribution of mode n from the new factor -------------------
+    // ---- 5. distribution of mode n from the new factor -------------------
     if (dp->sampler != CPD_SAMPLER_UNIFORM) {
-      err = refresh_cdf(dp, S, n);
+      err = refresh_cdf<RT>(dp, S, n);
       if (err) break;
     }
+    __syncthreads();
   }
   if (tid == 0) {
     if (args.op == OP_STEP || args.op == OP_REPLAY) st->t = t0 + done;
@@ -596,18 +921,30 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
   }
 }
 
-// Host-side launcher (declared in cpd_runtime.hpp).
-hipError_t launch_chain_kernel(const ChainDesc* descs, int nchains, size_t lds_bytes,
-                               const StepArgs& args, hipStream_t stream) {
+// Host-side launcher (declared in cpd_runtime.hpp).  rt = the largest
+// number of rank tiles among the descriptors.
+template <int RT>
+static hipError_t launch_rt(const ChainDesc* descs, int nchains, size_t lds_bytes,
+                            const StepArgs& args, hipStream_t stream) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)chain_kernel,
+    hipError_t e = hipFuncSetAttribute((const void*)chain_kernel<RT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(chain_kernel, dim3(nchains), dim3(kBlock), lds_bytes, stream, descs, args);
+  hipLaunchKernelGGL(chain_kernel<RT>, dim3(nchains), dim3(kBlock), lds_bytes, stream, descs, args);
   return hipGetLastError();
+}
+
+hipError_t launch_chain_kernel(const ChainDesc* descs, int nchains, int rt, size_t lds_bytes,
+                               const StepArgs& args, hipStream_t stream) {
+  switch (rt) {
+    case 1: return launch_rt<1>(descs, nchains, lds_bytes, args, stream);
+    case 2: return launch_rt<2>(descs, nchains, lds_bytes, args, stream);
+    case 3: return launch_rt<3>(descs, nchains, lds_bytes, args, stream);
+    default: return launch_rt<4>(descs, nchains, lds_bytes, args, stream);
+  }
 }
 
 }  // namespace cpdmi
