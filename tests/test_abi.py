@@ -55,5 +55,9 @@ def test_workspace_size_and_validation():
         P.cpd_workspace_size(p, P.make_options(sampler=7))
     # a plan that cannot fit the on-chip budget is refused up front
     with pytest.raises(P.CpdError) as e:
-        P.cpd_workspace_size(P.make_problem([4096, 4096, 8], 64, 4096), o)
+        P.cpd_workspace_size(P.make_problem([4096, 64, 64], 64, 4096), o)
     assert "LDS" in str(e.value)
+    # every mode-major copy must stay addressable with 32-bit byte offsets
+    with pytest.raises(P.CpdError) as e:
+        P.cpd_workspace_size(P.make_problem([4096, 4096, 128], 8, 64), o)
+    assert "4 GiB" in str(e.value)
