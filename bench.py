@@ -25,7 +25,31 @@ if ROOT not in sys.path:
 
 METRIC = "SGD steps/s + HBM GB/s (sampled gradient); solves/s & p99 time-to-fit 0.99"
 HBM_PEAK_GBPS = 8000.0
-ETA = 0.5
+ETA = 3.0
+
+# HBM traffic of the step kernel on this workload, from FETCH_SIZE and WRITE_SIZE counter runs
+# scaled by a 256 MiB device copy (FETCH x2.000, WRITE x1.000), 5000-step dispatch.  Valid only
+# for the kernel sources it was taken on: reported as null once either hash differs.
+MEASURED_TRAFFIC = {
+    "bytes_per_step": 136725.0 * 1024 / 5000,
+    "sources": {
+        "paper_2103_04081_amd/csrc/step_kernel.hip":
+            "9f641870f3c6d876e018f1ec215f6e2ac6cbcf8b2ddd96be9fcda6d086824be1",
+        "paper_2103_04081_amd/csrc/cpd_internal.hpp":
+            "b10b42f246f13fbb4a6409fb7c1e7e6d26eb9c9f2c102a5d2395caf95d8ed4fc",
+    },
+    "profile": "profiles/chain_kernel_300cube_R10_B256_f32.md",
+}
+
+
+def measured_traffic_per_step():
+    """Counter-measured HBM bytes per step, or None if the kernel changed since."""
+    import hashlib
+    for rel, want in MEASURED_TRAFFIC["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != want:
+                return None
+    return MEASURED_TRAFFIC["bytes_per_step"]
 
 
 def step_bytes(dims, R, B, elem):
@@ -52,6 +76,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fit", action="store_true", help="skip the time-to-fit runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the timed region, one device copy of this many MiB (a "
+                         "known-size kernel to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -114,7 +141,15 @@ def main():
     achieved = sb * args.steps / sec / 1e9
     fit_after = dec.fit()
     dec.close()
+    if args.calib_copy_mb:
+        nbytes = args.calib_copy_mb << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
+    traffic = measured_traffic_per_step()
     extra = {}
     if not args.no_fit:
         extra["time_to_fit"] = time_to_fit(make, target=0.99, every=25, max_steps=40000)
@@ -133,13 +168,16 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "300x300x300 FP32 tensor, R=10, B=256, rho=0.6, 10% rows x20, "
-                               "SNR 30 dB; EAdawsCPD (Euclidean sampler, AdaGrad eta=0.5, b=0)",
+                               f"SNR 30 dB; EAdawsCPD (Euclidean sampler, AdaGrad eta={ETA}, b=0)",
                    "sampler": args.sampler, "global_batch": B, "rank": R,
                    "parallelism": "single GPU, one persistent workgroup per decomposition"},
         "hbm_gbps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "bytes_per_step": sb, "kernel": "chain_kernel"},
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": (None if traffic is None else traffic * args.steps),
+                     "traffic_per_step": traffic, "bytes_per_step": sb,
+                     "steps_per_launch": args.steps, "kernel": "chain_kernel<1>",
+                     "counters": MEASURED_TRAFFIC["profile"]},
         "fit_after_timed_steps": fit_after,
     }
     out.update(extra)
