@@ -98,6 +98,11 @@ typedef struct cpd_options {
   int32_t fit_every;               /* steps between fit checks (serving/batch) */
   double fit_target;               /* stop when fit >= target (serving/batch) */
   int64_t max_steps;               /* stop after this many steps (serving/batch) */
+  int32_t ksplit[CPD_MAX_MODES];   /* tile choice of the mode-k contraction: the number
+                                      of parts its fibre range is split into across
+                                      waves (0 = library default; see
+                                      cpd_batch_member_info).  Results depend on it
+                                      only through the FP32 summation order. */
 } cpd_options;
 
 typedef struct cpd_handle cpd_handle;
@@ -191,6 +196,84 @@ CPD_API cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes)
 
 /* Release the handle (the workspace stays the caller's). */
 CPD_API cpd_status cpd_destroy(cpd_handle* h);
+
+/* ------------------------------------------------------------------------
+ * Batched decompositions: many independent problems (different sizes,
+ * ranks, samplers) advanced together, one persistent workgroup per problem,
+ * every member in the same launch (one launch per 16-column rank-tile class,
+ * run concurrently).  Each member runs exactly the computation of a single
+ * handle created with the same problem and options (including the ksplit
+ * the batch reports), so its results are those of that handle, bit for bit.
+ * Members stop on their own: after a fit check with fit >= fit_target, or
+ * once t reaches max_steps (options of that member).
+ * ------------------------------------------------------------------------ */
+typedef struct cpd_batch cpd_batch;
+
+typedef struct cpd_member_info {
+  int64_t t;                      /* steps taken */
+  double fit;                     /* last fit check */
+  int32_t done;                   /* stopped (target fit, step limit or error) */
+  cpd_status status;              /* sticky device status of the member */
+  int64_t t_done;                 /* t at the check that stopped it */
+  double seconds_done;            /* device time from its first distributions to that check */
+  int32_t ksplit[CPD_MAX_MODES];  /* tile choice used for each mode */
+} cpd_member_info;
+
+/* Device bytes cpd_batch_create needs for these members. */
+CPD_API cpd_status cpd_batch_workspace_size(const cpd_problem* ps, const cpd_options* os,
+                                            int32_t count, size_t* bytes);
+
+/*
+ * cpd_batch_create: count members, problem ps[i] with options os[i].
+ *   X[i]        member i's dense tensor (layout as cpd_init), all of element
+ *               type x_dtype in space x_space.
+ *   A0          count * CPD_MAX_MODES host pointers: A0[i*CPD_MAX_MODES + k]
+ *               is member i's initial factor k (dims[k] x R FP32).
+ *   ws          caller-owned device workspace of cpd_batch_workspace_size
+ *               bytes, 256-byte aligned; must outlive the batch.
+ *   tune        1: time the candidate tile choices (ksplit) of every mode on
+ *               the members themselves, keep the fastest, then restart each
+ *               member from A0.  Choices are cached per (mode size, rank, B,
+ *               storage) for the life of the process.  0: library defaults
+ *               (or os[i].ksplit where given).
+ * All members must share os[i].fit_every (the round length).
+ * Errors: as cpd_init, per member (the message names it).
+ */
+CPD_API cpd_status cpd_batch_create(const cpd_problem* ps, const cpd_options* os, int32_t count,
+                                    const void* const* X, int32_t x_dtype, int32_t x_space,
+                                    const float* const* A0, void* ws, size_t ws_bytes,
+                                    void* stream, int32_t tune, cpd_batch** out);
+
+/* Every member not yet done advances nsteps (capped at its max_steps).  Async. */
+CPD_API cpd_status cpd_batch_step(cpd_batch* b, int64_t nsteps);
+
+/*
+ * cpd_batch_fits: fit check of every member not yet done (one launch for all),
+ * marking members that reach their target as done; fits[i] receives member
+ * i's last fit.  Synchronous.
+ */
+CPD_API cpd_status cpd_batch_fits(cpd_batch* b, double* fits);
+
+/*
+ * cpd_batch_run: replay rounds of {fit_every steps of every member, fit
+ * check of every member} from a captured HIP graph until every member is
+ * done or max_rounds rounds ran.  *remaining receives the number of members
+ * not done.  Synchronous.
+ */
+CPD_API cpd_status cpd_batch_run(cpd_batch* b, int64_t max_rounds, int32_t* remaining);
+
+/* Wait for the batch's work; returns the first member error, else CPD_OK. */
+CPD_API cpd_status cpd_batch_sync(cpd_batch* b);
+
+/* Member i's counters and tile choices.  Synchronous. */
+CPD_API cpd_status cpd_batch_member_info(cpd_batch* b, int32_t i, cpd_member_info* out);
+
+/* Copy member i's factor n to dst (host or device).  Synchronous. */
+CPD_API cpd_status cpd_batch_read_factors(cpd_batch* b, int32_t i, int32_t n, float* dst,
+                                          int32_t dst_space);
+
+/* Release the batch (the workspace stays the caller's). */
+CPD_API cpd_status cpd_batch_destroy(cpd_batch* b);
 
 #ifdef __cplusplus
 }

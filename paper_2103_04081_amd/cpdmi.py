@@ -49,7 +49,13 @@ class cpd_options(ctypes.Structure):
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("storage", ctypes.c_int32), ("nonneg", ctypes.c_int32),
                 ("fit_every", ctypes.c_int32), ("fit_target", ctypes.c_double),
-                ("max_steps", ctypes.c_int64)]
+                ("max_steps", ctypes.c_int64), ("ksplit", ctypes.c_int32 * MAX_MODES)]
+
+
+class cpd_member_info(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("fit", ctypes.c_double), ("done", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("t_done", ctypes.c_int64),
+                ("seconds_done", ctypes.c_double), ("ksplit", ctypes.c_int32 * MAX_MODES)]
 
 
 _lib = None
@@ -100,11 +106,19 @@ def _extra_signatures(L):
     H = ctypes.c_void_p
     P = ctypes.POINTER
     st = ctypes.c_int32
+    vp = ctypes.c_void_p
     extra = {
-        "cpd_batch_create": (st, [P(H), ctypes.c_int32, ctypes.c_void_p, P(H)]),
+        "cpd_batch_workspace_size": (st, [P(cpd_problem), P(cpd_options), ctypes.c_int32,
+                                          P(ctypes.c_size_t)]),
+        "cpd_batch_create": (st, [P(cpd_problem), P(cpd_options), ctypes.c_int32, P(vp),
+                                  ctypes.c_int32, ctypes.c_int32, P(vp), vp, ctypes.c_size_t, vp,
+                                  ctypes.c_int32, P(H)]),
         "cpd_batch_step": (st, [H, ctypes.c_int64]),
         "cpd_batch_fits": (st, [H, P(ctypes.c_double)]),
+        "cpd_batch_run": (st, [H, ctypes.c_int64, P(ctypes.c_int32)]),
         "cpd_batch_sync": (st, [H]),
+        "cpd_batch_member_info": (st, [H, ctypes.c_int32, P(cpd_member_info)]),
+        "cpd_batch_read_factors": (st, [H, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32]),
         "cpd_batch_destroy": (st, [H]),
     }
     for name, (res, args) in extra.items():
@@ -136,7 +150,7 @@ def make_problem(dims, R, B, seed=0, stream_id=0):
 
 def make_options(sampler="euclidean", rule="adagrad", alpha=0.0, eta=1.0, b=0.0, beta=0.0,
                  gamma=1.0, storage="f32", nonneg=False, fit_every=25, fit_target=0.99,
-                 max_steps=0):
+                 max_steps=0, ksplit=None):
     o = cpd_options()
     o.sampler = SAMPLER[sampler] if isinstance(sampler, str) else int(sampler)
     o.rule = RULE[rule] if isinstance(rule, str) else int(rule)
@@ -146,6 +160,8 @@ def make_options(sampler="euclidean", rule="adagrad", alpha=0.0, eta=1.0, b=0.0,
     o.fit_every = int(fit_every)
     o.fit_target = float(fit_target)
     o.max_steps = int(max_steps)
+    for k, v in enumerate(ksplit or []):
+        o.ksplit[k] = int(v)
     return o
 
 
@@ -224,7 +240,160 @@ def cpd_destroy(h):
     return check(lib().cpd_destroy(h), "cpd_destroy")
 
 
-# --- convenience object -----------------------------------------------------
+def cpd_batch_workspace_size(problems, options):
+    n = len(problems)
+    P = (cpd_problem * n)(*problems)
+    O = (cpd_options * n)(*options)
+    out = ctypes.c_size_t()
+    check(lib().cpd_batch_workspace_size(P, O, n, ctypes.byref(out)), "cpd_batch_workspace_size")
+    return out.value
+
+
+def cpd_batch_create(problems, options, X_ptrs, x_dtype, x_space, A0_ptrs, ws_ptr, ws_bytes,
+                     stream, tune):
+    """A0_ptrs: per member a list of N host addresses (padded to MAX_MODES here)."""
+    n = len(problems)
+    P = (cpd_problem * n)(*problems)
+    O = (cpd_options * n)(*options)
+    xs = (ctypes.c_void_p * n)(*X_ptrs)
+    flat = []
+    for ptrs in A0_ptrs:
+        flat.extend(list(ptrs) + [None] * (MAX_MODES - len(ptrs)))
+    a0 = (ctypes.c_void_p * len(flat))(*flat)
+    h = ctypes.c_void_p()
+    check(lib().cpd_batch_create(P, O, n, xs, x_dtype, x_space, a0, ctypes.c_void_p(ws_ptr),
+                                 ws_bytes, ctypes.c_void_p(stream), int(tune), ctypes.byref(h)),
+          "cpd_batch_create")
+    return h
+
+
+def cpd_batch_step(b, nsteps):
+    return check(lib().cpd_batch_step(b, int(nsteps)), "cpd_batch_step")
+
+
+def cpd_batch_fits(b, count):
+    out = (ctypes.c_double * count)()
+    check(lib().cpd_batch_fits(b, out), "cpd_batch_fits")
+    return list(out)
+
+
+def cpd_batch_run(b, max_rounds):
+    left = ctypes.c_int32()
+    check(lib().cpd_batch_run(b, int(max_rounds), ctypes.byref(left)), "cpd_batch_run")
+    return left.value
+
+
+def cpd_batch_sync(b):
+    return check(lib().cpd_batch_sync(b), "cpd_batch_sync")
+
+
+def cpd_batch_member_info(b, i):
+    info = cpd_member_info()
+    check(lib().cpd_batch_member_info(b, int(i), ctypes.byref(info)), "cpd_batch_member_info")
+    return info
+
+
+def cpd_batch_read_factors(b, i, n, dst_ptr, space):
+    return check(lib().cpd_batch_read_factors(b, int(i), int(n), ctypes.c_void_p(dst_ptr), space),
+                 "cpd_batch_read_factors")
+
+
+def cpd_batch_destroy(b):
+    return check(lib().cpd_batch_destroy(b), "cpd_batch_destroy")
+
+
+# --- convenience objects ----------------------------------------------------
+
+def _host_tensor(X):
+    Xn = np.asarray(X)
+    x_dtype = CPD_F64 if Xn.dtype == np.float64 else CPD_F32
+    Xf = np.asfortranarray(Xn.astype(np.float64 if x_dtype == CPD_F64 else np.float32, copy=False))
+    return Xf, x_dtype
+
+
+def _workspace(nbytes, device):
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    return ws, (ws.data_ptr() + 255) // 256 * 256
+
+
+class Batch:
+    """Many decompositions advanced together (one persistent launch).
+
+    ``members``: list of dicts with keys X (numpy tensor), A0 (list of
+    factors), B, and any option of :func:`make_options` plus seed and
+    stream_id.  All members share ``storage`` and ``fit_every``.
+    """
+
+    def __init__(self, members, *, tune=True, device="cuda"):
+        self.device = torch.device(device)
+        self.members = []
+        problems, options, xs, a0s, keep = [], [], [], [], []
+        x_dtype = None
+        opt_keys = ("sampler", "rule", "alpha", "eta", "b", "beta", "gamma", "storage", "nonneg",
+                    "fit_every", "fit_target", "max_steps", "ksplit")
+        for m in members:
+            Xf, xd = _host_tensor(m["X"])
+            if x_dtype is None:
+                x_dtype = xd
+            if xd != x_dtype:
+                Xf, xd = Xf.astype(np.float64 if x_dtype == CPD_F64 else np.float32), x_dtype
+                Xf = np.asfortranarray(Xf)
+            A0 = [np.ascontiguousarray(np.asarray(a, dtype=np.float32)) for a in m["A0"]]
+            dims = list(Xf.shape)
+            R = A0[0].shape[1]
+            problems.append(make_problem(dims, R, m["B"], m.get("seed", 0), m.get("stream_id", 0)))
+            options.append(make_options(**{k: m[k] for k in opt_keys if k in m}))
+            xs.append(Xf.ctypes.data)
+            a0s.append([a.ctypes.data for a in A0])
+            keep.append((Xf, A0))
+            self.members.append({"dims": dims, "R": R})
+        self.count = len(problems)
+        self.ws_bytes = cpd_batch_workspace_size(problems, options)
+        self.ws, self.ws_ptr = _workspace(self.ws_bytes, self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = cpd_batch_create(problems, options, xs, x_dtype, CPD_HOST, a0s, self.ws_ptr,
+                                  self.ws_bytes, self.stream.cuda_stream, tune)
+        del keep
+
+    def step(self, nsteps):
+        cpd_batch_step(self.h, nsteps)
+
+    def fits(self):
+        return cpd_batch_fits(self.h, self.count)
+
+    def run(self, max_rounds):
+        return cpd_batch_run(self.h, max_rounds)
+
+    def sync(self):
+        cpd_batch_sync(self.h)
+
+    def info(self, i):
+        inf = cpd_batch_member_info(self.h, i)
+        N = len(self.members[i]["dims"])
+        return {"t": inf.t, "fit": inf.fit, "done": bool(inf.done), "status": inf.status,
+                "t_done": inf.t_done, "seconds_done": inf.seconds_done,
+                "ksplit": [inf.ksplit[k] for k in range(N)]}
+
+    def factors(self, i):
+        m = self.members[i]
+        out = []
+        for k, I in enumerate(m["dims"]):
+            a = np.empty((I, m["R"]), dtype=np.float32)
+            cpd_batch_read_factors(self.h, i, k, a.ctypes.data, CPD_HOST)
+            out.append(a)
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            cpd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 class Decomposition:
     """One decomposition bound to a torch-allocated device workspace.
@@ -236,7 +405,7 @@ class Decomposition:
 
     def __init__(self, X, A0, *, B, R=None, sampler="euclidean", rule="adagrad", alpha=0.0,
                  eta=1.0, b=0.0, beta=0.0, gamma=1.0, storage="f32", nonneg=False, seed=0,
-                 stream_id=0, device="cuda", dims=None):
+                 stream_id=0, device="cuda", dims=None, ksplit=None):
         self.device = torch.device(device)
         if isinstance(X, torch.Tensor):
             assert X.is_cuda and X.is_contiguous()
@@ -256,7 +425,8 @@ class Decomposition:
         R = self.A0[0].shape[1] if R is None else int(R)
         self.dims, self.R, self.B = dims, R, int(B)
         self.problem = make_problem(dims, R, B, seed, stream_id)
-        self.options = make_options(sampler, rule, alpha, eta, b, beta, gamma, storage, nonneg)
+        self.options = make_options(sampler, rule, alpha, eta, b, beta, gamma, storage, nonneg,
+                                    ksplit=ksplit)
         self.ws_bytes = cpd_workspace_size(self.problem, self.options)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()

@@ -56,6 +56,15 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
       return CPD_E_INVALID;
     }
   }
+  for (int k = 0; k < p->N; ++k) {
+    const int ks = o->ksplit[k];
+    const int mx = max_ksplit(p->dims[k], o->storage, p->B, p->R);
+    if (ks < 0 || ks > mx) {
+      *why = "ksplit[" + std::to_string(k) + "] must be 0 (default) or in [1, " +
+             std::to_string(mx) + "] for this mode";
+      return CPD_E_INVALID;
+    }
+  }
   const size_t es = o->storage == CPD_BF16 ? 2 : 4;
   size_t off = 0;
   w->state = off;
@@ -105,7 +114,7 @@ void fill_desc(const cpd_problem* p, const cpd_options* o, const WsPlan& w, char
   for (int k = 0; k < p->N; ++k) {
     d->dims[k] = p->dims[k];
     d->ld[k] = w.ld[k];
-    d->ksplit[k] = host_ksplit(p->dims[k], o->storage, p->B, p->R);
+    d->ksplit[k] = o->ksplit[k] > 0 ? o->ksplit[k] : host_ksplit(p->dims[k], o->storage, p->B, p->R);
     d->X[k] = base + w.X[k];
     d->A[k] = (float*)(base + w.A[k]);
     d->S[k] = (float*)(base + w.S[k]);
@@ -125,7 +134,70 @@ void fill_desc(const cpd_problem* p, const cpd_options* o, const WsPlan& w, char
   d->state = (ChainState*)(base + w.state);
   d->parts = (double*)(base + w.parts);
   d->active = 1;
+  d->autostop = 0;
   d->step_limit = 0;
+  d->fit_target = 0.0;
+}
+
+// Copy the tensor and the initial factors of one decomposition into its
+// workspace (zeroed first) and write its descriptor to d_desc.  Does not
+// build the distributions.  Enqueued on `stream`; host input is staged
+// synchronously in chunks.
+cpd_status init_member(const cpd_problem* p, const cpd_options* o, const void* X, int x_dtype,
+                       int x_space, const float* const* A0, const WsPlan& w, char* base,
+                       hipStream_t stream, ChainDesc* desc, ChainDesc* d_desc) {
+  hipError_t e = hipMemsetAsync(base, 0, w.total, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(workspace)");
+  e = hipMemcpyAsync(d_desc, desc, sizeof(ChainDesc), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(desc)");
+  for (int k = 0; k < p->N; ++k) {
+    e = hipMemcpyAsync(desc->A[k], A0[k], sizeof(float) * (size_t)p->dims[k] * p->R,
+                       hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(A0)");
+  }
+  if (x_space == CPD_DEVICE) {
+    e = launch_layout_from_dense(X, x_dtype, *desc, stream);
+    if (e != hipSuccess) return hip_fail(e, "layout kernels");
+    return CPD_OK;
+  }
+  // host input: round to the storage type on the host, copy 0 by rows
+  const int I0 = p->dims[0];
+  const int64_t rows = w.rows[0];
+  const size_t es = o->storage == CPD_BF16 ? 2 : 4;
+  const int64_t chunk = std::max<int64_t>(1, ((int64_t)8 << 20) / ((int64_t)I0 * es));
+  std::vector<unsigned char> buf((size_t)std::min(chunk, rows) * I0 * es);
+  for (int64_t r0 = 0; r0 < rows; r0 += chunk) {
+    const int64_t nr = std::min(chunk, rows - r0);
+    const int64_t b0 = r0 * I0, cnt = nr * I0;
+    for (int64_t i = 0; i < cnt; ++i) {
+      const float v = x_dtype == CPD_F64 ? (float)((const double*)X)[b0 + i]
+                                         : ((const float*)X)[b0 + i];
+      if (es == 2) ((uint16_t*)buf.data())[i] = f32_to_bf16_rne(v);
+      else ((float*)buf.data())[i] = v;
+    }
+    e = hipMemcpy2DAsync((char*)desc->X[0] + (size_t)r0 * w.ld[0] * es, (size_t)w.ld[0] * es,
+                         buf.data(), (size_t)I0 * es, (size_t)I0 * es, (size_t)nr,
+                         hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync(X)");
+    // the staging buffer is reused by the next chunk
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  e = launch_layout_from_copy0(*desc, stream);
+  if (e != hipSuccess) return hip_fail(e, "layout kernels");
+  return CPD_OK;
+}
+
+cpd_status check_input_kinds(int x_dtype, int x_space) {
+  if (x_dtype != CPD_F32 && x_dtype != CPD_F64) {
+    set_error("x_dtype must be CPD_F32 or CPD_F64");
+    return CPD_E_INVALID;
+  }
+  if (x_space != CPD_HOST && x_space != CPD_DEVICE) {
+    set_error("x_space must be CPD_HOST or CPD_DEVICE");
+    return CPD_E_INVALID;
+  }
+  return CPD_OK;
 }
 
 }  // namespace cpdmi
@@ -153,18 +225,24 @@ static cpd_status read_state(cpd_handle* h, ChainState* st) {
   return CPD_OK;
 }
 
+namespace cpdmi {
+void describe_status(cpd_status s) {
+  switch (s) {
+    case CPD_OK: break;
+    case CPD_E_RANK_DEFICIENT: set_error("a factor is rank deficient (leverage scores undefined)"); break;
+    case CPD_E_DEGENERATE: set_error("all sampling weights of a factor are zero or not finite"); break;
+    case CPD_E_DIVERGED: set_error("a factor became non-finite (step too large?)"); break;
+    case CPD_E_INVALID: set_error("a replayed index is outside its mode"); break;
+    default: set_error("device error " + std::to_string(s));
+  }
+}
+}  // namespace cpdmi
+
 static cpd_status device_status(cpd_handle* h) {
   ChainState st;
   cpd_status s = read_state(h, &st);
   if (s != CPD_OK) return s;
-  if (st.status != 0) {
-    switch (st.status) {
-      case CPD_E_RANK_DEFICIENT: set_error("a factor is rank deficient (leverage scores undefined)"); break;
-      case CPD_E_DEGENERATE: set_error("all sampling weights of a factor are zero or not finite"); break;
-      case CPD_E_DIVERGED: set_error("a factor became non-finite (step too large?)"); break;
-      default: set_error("device error " + std::to_string(st.status));
-    }
-  }
+  describe_status(st.status);
   return st.status;
 }
 
@@ -217,14 +295,8 @@ cpd_status cpd_init(const cpd_problem* p, const cpd_options* o, const void* X, i
       set_error(why);
       return s;
     }
-    if (x_dtype != CPD_F32 && x_dtype != CPD_F64) {
-      set_error("x_dtype must be CPD_F32 or CPD_F64");
-      return CPD_E_INVALID;
-    }
-    if (x_space != CPD_HOST && x_space != CPD_DEVICE) {
-      set_error("x_space must be CPD_HOST or CPD_DEVICE");
-      return CPD_E_INVALID;
-    }
+    s = check_input_kinds(x_dtype, x_space);
+    if (s != CPD_OK) return s;
     if (((uintptr_t)ws) % kAlign) {
       set_error("workspace must be 256-byte aligned");
       return CPD_E_INVALID;
@@ -262,43 +334,11 @@ cpd_status cpd_init(const cpd_problem* p, const cpd_options* o, const void* X, i
       delete h;
       return r;
     };
-    e = hipMemsetAsync(ws, 0, w.total, h->stream);
-    if (e != hipSuccess) return fail(e, "hipMemsetAsync(workspace)");
-    e = hipMemcpyAsync(h->d_desc, &h->desc, sizeof(ChainDesc), hipMemcpyHostToDevice, h->stream);
-    if (e != hipSuccess) return fail(e, "hipMemcpyAsync(desc)");
-    for (int k = 0; k < p->N; ++k) {
-      e = hipMemcpyAsync(h->desc.A[k], A0[k], sizeof(float) * (size_t)p->dims[k] * p->R,
-                         hipMemcpyHostToDevice, h->stream);
-      if (e != hipSuccess) return fail(e, "hipMemcpyAsync(A0)");
-    }
-    if (x_space == CPD_DEVICE) {
-      e = launch_layout_from_dense(X, x_dtype, h->desc, h->stream);
-      if (e != hipSuccess) return fail(e, "layout kernels");
-    } else {
-      // host input: round to the storage type on the host, copy 0 by rows
-      const int I0 = p->dims[0];
-      const int64_t rows = w.rows[0];
-      const size_t es = o->storage == CPD_BF16 ? 2 : 4;
-      const int64_t chunk = std::max<int64_t>(1, ((int64_t)8 << 20) / ((int64_t)I0 * es));
-      std::vector<unsigned char> buf((size_t)std::min(chunk, rows) * I0 * es);
-      for (int64_t r0 = 0; r0 < rows; r0 += chunk) {
-        const int64_t nr = std::min(chunk, rows - r0);
-        const int64_t base = r0 * I0, cnt = nr * I0;
-        for (int64_t i = 0; i < cnt; ++i) {
-          const float v = x_dtype == CPD_F64 ? (float)((const double*)X)[base + i]
-                                             : ((const float*)X)[base + i];
-          if (es == 2) ((uint16_t*)buf.data())[i] = f32_to_bf16_rne(v);
-          else ((float*)buf.data())[i] = v;
-        }
-        e = hipMemcpy2DAsync((char*)h->desc.X[0] + (size_t)r0 * w.ld[0] * es, (size_t)w.ld[0] * es,
-                             buf.data(), (size_t)I0 * es, (size_t)I0 * es, (size_t)nr,
-                             hipMemcpyHostToDevice, h->stream);
-        if (e != hipSuccess) return fail(e, "hipMemcpy2DAsync(X)");
-        e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) return fail(e, "hipStreamSynchronize");
-      }
-      e = launch_layout_from_copy0(h->desc, h->stream);
-      if (e != hipSuccess) return fail(e, "layout kernels");
+    s = init_member(p, o, X, x_dtype, x_space, A0, w, h->ws, h->stream, &h->desc, h->d_desc);
+    if (s != CPD_OK) {
+      (void)hipStreamSynchronize(h->stream);
+      delete h;
+      return s;
     }
     StepArgs a{};
     a.op = OP_REFRESH;

@@ -30,11 +30,15 @@ enum Op : int32_t { OP_STEP = 0, OP_SAMPLE = 1, OP_REPLAY = 2, OP_REFRESH = 3 };
 struct ChainState {
   int64_t t;          // steps taken
   int32_t status;     // sticky cpd_status of the device side
-  int32_t pad0;
+  int32_t done;       // batched/served members: stopped (target fit or step limit)
   double fit;         // last fit computed
   double x2;          // ||X||^2 of the stored tensor
   double inner;       // last <X, [[A]]>
   double xhat2;       // last ||[[A]]||^2
+  int64_t ticks;      // wall-clock ticks of this chain's last step launch
+  int64_t clock_start;  // wall clock when the distributions were first built
+  int64_t clock_done;   // wall clock when done was set
+  int64_t t_done;       // t when done was set
 };
 
 // Everything a kernel needs to run one decomposition.  Lives in device
@@ -58,19 +62,22 @@ struct ChainDesc {
   ChainState* state;
   double* parts;                       // kFitParts partial sums (fit / norm)
   int32_t active;                      // batched path: 0 = slot idle
-  int32_t pad2;
-  int64_t step_limit;                  // batched path: stop at this t
+  int32_t autostop;                    // fit kernels set state->done at the target
+  int64_t step_limit;                  // stop stepping at this t (0 = none)
+  double fit_target;                   // autostop: done once fit >= fit_target (if > 0)
 };
 
 struct StepArgs {
   int64_t nsteps;
   int32_t op;
-  int32_t replay_mode;
+  int32_t replay_mode;  // OP_REPLAY: the mode
   uint64_t sample_t;
   const int32_t* replay_idx;
   int32_t* out_idx;
   double* out_p;
   int32_t* out_mode;
+  int32_t force_mode1;  // OP_STEP timing runs: 1 + the mode every step uses; 0 = drawn
+  int32_t pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -152,6 +159,21 @@ __host__ __device__ inline float bf16_to_f32(uint16_t h) {
 // Per-mode contraction split: the I_n x R output is cut into column tiles of
 // 16 * VW entries (VW = 1 for FP32, 2 for BF16 storage), one tile per wave;
 // with fewer tiles than waves the B dimension is split as well.
+// Largest K-split of mode n's contraction the step kernel supports: every
+// (row tile, K part) pair needs its own wave, and every part at least one
+// chunk of fibres.
+inline int max_ksplit(int In, int dtype, int B, int R) {
+  const int vw = dtype == CPD_BF16 ? 2 : 1;
+  const int nst = (In + 16 * vw - 1) / (16 * vw);
+  const int rt = (R + 15) / 16;
+  const int u = kChunkSteps / vw / rt;
+  const int chunks = (int)(((B + kFibrePad - 1) / kFibrePad) * kFibrePad / 4 / u);
+  int m = kWaves / nst;
+  if (m > chunks) m = chunks;
+  return m < 1 ? 1 : m;
+}
+
+// Default K-split when no tuned value is given.
 inline int host_ksplit(int In, int dtype, int B, int R) {
   const int vw = dtype == CPD_BF16 ? 2 : 1;
   const int nst = (In + 16 * vw - 1) / (16 * vw);

@@ -35,6 +35,14 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* ou
 void fill_desc(const cpd_problem* p, const cpd_options* o, const WsPlan& w, char* base,
                ChainDesc* d);
 
+cpd_status init_member(const cpd_problem* p, const cpd_options* o, const void* X, int x_dtype,
+                       int x_space, const float* const* A0, const WsPlan& w, char* base,
+                       hipStream_t stream, ChainDesc* desc, ChainDesc* d_desc);
+cpd_status check_input_kinds(int x_dtype, int x_space);
+
+// Message for a sticky device status (sets the thread's last error).
+void describe_status(cpd_status s);
+
 void set_error(const std::string& msg);
 cpd_status hip_fail(hipError_t e, const char* what);
 

@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kFitBlock / 64];
   const ChainDesc* dp = descs + blockIdx.y;
-  if (!dp->active) return;
+  if (!dp->active || (INNER && dp->state->done)) return;
   const int N = dp->N, R = dp->R, I0 = dp->dims[0], ld0 = dp->ld[0];
   const T* X0 = (const T*)dp->X[0];
   // A^(1) rows: staged in LDS when they fit, else read through the caches
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
                                                          int nparts_per_chain) {
   __shared__ double red[16];
   const ChainDesc* dp = descs + blockIdx.x;
-  if (!dp->active) return;
+  if (!dp->active || (INNER && dp->state->done)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double s = 0.0;
   for (int p = threadIdx.x; p < nparts_per_chain; p += blockDim.x) s += dp->parts[p];
@@ -248,6 +248,12 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
     st->inner = total;
     st->xhat2 = xh;
     st->fit = 1.0 - (st->x2 - 2.0 * total + xh) / st->x2;
+    if (dp->autostop && ((dp->fit_target > 0.0 && st->fit >= dp->fit_target) ||
+                         (dp->step_limit > 0 && st->t >= dp->step_limit) || st->status != 0)) {
+      st->done = 1;
+      st->t_done = st->t;
+      st->clock_done = (int64_t)wall_clock64();
+    }
   }
 }
 

@@ -689,6 +689,8 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
   if (!dp->active) return;
   ChainState* st = dp->state;
   if (args.op != OP_SAMPLE && args.op != OP_REFRESH && st->status != 0) return;
+  if (args.op == OP_STEP && (st->done || args.force_mode1 > dp->N)) return;
+  const int64_t clock0 = (int64_t)wall_clock64();
   const int tid = threadIdx.x;
   const int N = dp->N, R = dp->R, B = dp->B;
   const LdsPlan P = lds_plan(N, dp->dims, R, B, RT);
@@ -740,7 +742,10 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
       err = refresh_cdf<RT>(dp, S, n);
       __syncthreads();
     }
-    if (tid == 0 && err) st->status = err;
+    if (tid == 0) {
+      if (err) st->status = err;
+      if (st->clock_start == 0) st->clock_start = clock0;
+    }
     return;
   }
 
@@ -792,7 +797,7 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
         }
         __syncthreads();
       }
-      n = (int)mulhi_u64(words[0], (uint64_t)N);
+      n = args.force_mode1 ? args.force_mode1 - 1 : (int)mulhi_u64(words[0], (uint64_t)N);
       float pv[kPrefetch], ps[kPrefetch];
       prefetch_issue(dp, S, n, pv, ps);
       for (int d = 1 + tid; d < nd; d += kBlock) {
@@ -918,6 +923,7 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
   if (tid == 0) {
     if (args.op == OP_STEP || args.op == OP_REPLAY) st->t = t0 + done;
     if (err) st->status = err;
+    if (args.op == OP_STEP) st->ticks = (int64_t)wall_clock64() - clock0;
   }
 }
 

@@ -25,7 +25,10 @@ def declared_symbols():
 def test_headers_declare_entry_points():
     names = declared_symbols()
     for must in ("cpd_init", "cpd_sample", "cpd_step", "cpd_step_replay", "cpd_fit",
-                 "cpd_workspace_size", "cpd_read_state", "cpd_write_state"):
+                 "cpd_workspace_size", "cpd_read_state", "cpd_write_state", "cpd_destroy",
+                 "cpd_batch_workspace_size", "cpd_batch_create", "cpd_batch_step",
+                 "cpd_batch_fits", "cpd_batch_run", "cpd_batch_member_info",
+                 "cpd_batch_destroy"):
         assert must in names, must
 
 
@@ -61,3 +64,37 @@ def test_workspace_size_and_validation():
     with pytest.raises(P.CpdError) as e:
         P.cpd_workspace_size(P.make_problem([4096, 4096, 128], 8, 64), o)
     assert "4 GiB" in str(e.value)
+
+
+def test_ksplit_option_validation():
+    import paper_2103_04081_amd as P
+    p = P.make_problem([40, 300, 33], 10, 256)
+    # mode 0: 3 row tiles of 16 -> at most 2 parts per tile over 8 waves
+    P.cpd_workspace_size(p, P.make_options(ksplit=[2, 1, 0]))
+    with pytest.raises(P.CpdError) as e:
+        P.cpd_workspace_size(p, P.make_options(ksplit=[4, 0, 0]))
+    assert "ksplit[0]" in str(e.value)
+    with pytest.raises(P.CpdError):
+        P.cpd_workspace_size(p, P.make_options(ksplit=[0, 2, 0]))  # 19 tiles: no split
+    with pytest.raises(P.CpdError):
+        P.cpd_workspace_size(p, P.make_options(ksplit=[-1, 0, 0]))
+
+
+def test_batch_workspace_size():
+    import paper_2103_04081_amd as P
+    dims = [[50, 60, 70], [31, 17, 9, 12], [200, 100, 50]]
+    ps = [P.make_problem(d, 8, 128) for d in dims]
+    os_ = [P.make_options(storage="bf16") for _ in dims]
+    single = sum(P.cpd_workspace_size(p, o) for p, o in zip(ps, os_))
+    n = P.cpd_batch_workspace_size(ps, os_)
+    assert single < n < single + len(dims) * 256 + (1 << 16)
+    # members must share the storage type and the round length
+    with pytest.raises(P.CpdError):
+        P.cpd_batch_workspace_size(ps, os_[:2] + [P.make_options(storage="f32")])
+    with pytest.raises(P.CpdError):
+        P.cpd_batch_workspace_size(ps, os_[:2] + [P.make_options(storage="bf16", fit_every=7)])
+    # a bad member is named
+    bad = ps[:1] + [P.make_problem([31, 17, 9, 12], 0, 128)] + ps[2:]
+    with pytest.raises(P.CpdError) as e:
+        P.cpd_batch_workspace_size(bad, os_)
+    assert "member 1" in str(e.value)
