@@ -474,23 +474,6 @@ __device__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint6
       }
     }
   };
-  // AdaGrad accumulators of the entries this lane will update, loaded when
-  // the tile starts so the load latency hides behind the tile's chunks
-  float sv[RT][VW][4];
-  auto load_s = [&](int st) {
-    const int col0 = st * SW;
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int v = 0; v < VW; ++v)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int r = rt * 16 + 4 * fl + q;
-          const int i = col0 + cl * VW + v;
-          const bool in = ada && r < R && i < In;
-          sv[rt][v][q] = in ? S.sbuf()[i * ms + r] : 0.f;
-        }
-  };
   // -G^T of tile st into mbuf (the tile's rows were only read by this wave)
   auto store_neg_g = [&](int st) {
     const int col0 = st * SW;
@@ -520,7 +503,7 @@ __device__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint6
             // LDS only: a global store here would queue behind the fibre
             // loads in flight; the rows are written back after the phase
             const float g = -acc[rt][v][q];
-            float sacc = sv[rt][v][q];
+            float sacc = ada ? S.sbuf()[i * ms + r] : 0.f;
             const float an = update_entry(dp, mbuf[i * ms + r], g, sacc, alpha_t);
             if (ada) S.sbuf()[i * ms + r] = sacc;
             if (!isfinite(an)) bad = true;
@@ -539,7 +522,6 @@ __device__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint6
     const int st = st_first + it * kWaves;
     const int kq0 = (c0 + (c - it * nck)) * (U / 4);  // first group of 4 K-steps
     const uint32_t colb = (uint32_t)((st * SW + cl * VW) * (BF16 ? 2 : 4));
-    if (direct && c - it * nck == 0) load_s(st);
 #pragma unroll
     for (int u4 = 0; u4 < U / 4; ++u4) {
       const uint4 ob = *(const uint4*)(rowb + (kq0 + u4) * 16 + fl * 4);

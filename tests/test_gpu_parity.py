@@ -3,7 +3,8 @@
 Sizes are small enough for the oracle and still span several 16-wide MFMA
 tiles, ragged tails in every dimension (I_n, R and B not multiples of the
 tile sizes), 3- and 4-way tensors, one, two and three 16-row rank tiles,
-and both storage types.
+modes short enough to split the contraction over waves and long enough that
+each wave owns several row tiles, and both storage types.
 """
 
 import math
@@ -27,6 +28,9 @@ CASES = [
     ((64, 48, 50), 40, 17, "euclidean", "f32"),
     ((37, 45, 53), 7, 30, "euclidean", "bf16"),
     ((20, 24, 22, 18), 12, 40, "leverage", "bf16"),
+    # long modes: waves own several row tiles each (the unsplit contraction)
+    ((300, 20, 17), 6, 40, "euclidean", "f32"),
+    ((530, 12, 10), 5, 30, "leverage", "bf16"),
 ]
 IDS = [f"{'x'.join(map(str, c[0]))}-R{c[1]}-B{c[2]}-{c[3]}-{c[4]}" for c in CASES]
 

@@ -1,0 +1,76 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (one persistent workgroup per decomposition).
+
+The oracle cannot run these sizes for long, but one step of it only touches
+the sampled fibres, so it replays the device's draws step by step: sampling
+is checked bit for bit (against the oracle's sampler on the device's CDFs)
+and the iterates after a few steps within the FP32 tolerance.  Every member
+of the 64-tensor batch recipe is covered the same way."""
+
+import numpy as np
+import pytest
+
+import cpd_inputs as ci
+import oracle as O
+from parity_util import gpu_decomposition, rel, sample_from_cdfs
+
+pytestmark = pytest.mark.gpu
+
+
+def _replay(prob, B, steps, *, sampler, storage, eta, seed, stream_id=0, tol=1e-5, label=""):
+    dec = gpu_decomposition(prob, B, sampler=sampler, storage=storage, eta=eta, seed=seed,
+                            stream_id=stream_id)
+    orc = O.Oracle(prob["X"], prob["A0"], B=B, sampler=sampler, eta=eta, seed=seed,
+                   stream_id=stream_id)
+    N = len(prob["dims"])
+    for t in range(steps):
+        cdfs = [dec.cdf(n) for n in range(N)]
+        n, idx, p = dec.sample(t)
+        n2, idx2, p2 = sample_from_cdfs(cdfs, seed, stream_id, t, B)
+        assert n == n2 and np.array_equal(idx, idx2) and np.array_equal(p, p2), (label, t)
+        if sampler == "euclidean":
+            # the device's CDFs are the oracle's quantised distribution of the
+            # device's own current factors, bit for bit
+            A = dec.factors()
+            for k in range(N):
+                _, C_ref, _ = O.distribution(A[k].astype(np.float64), sampler)
+                assert np.array_equal(cdfs[k], C_ref), (label, t, k)
+        orc.step(replay=(n, idx))
+        dec.step(1)
+    A = dec.factors()
+    err = max(rel(A[k], orc.A[k]) for k in range(N))
+    print(f"{label}: {steps} steps, max rel err vs oracle {err:.3e}", flush=True)
+    assert err <= tol, label
+    dec.close()
+    return err
+
+
+def test_full_300cube_f32():
+    w = ci.workload(2)
+    _replay(w, w["B"], 20, sampler="euclidean", storage="f32", eta=3.0, seed=w["seed"],
+            label="300^3 R10 B256 f32")
+
+
+def test_full_300cube_leverage():
+    w = ci.workload(2)
+    _replay(w, w["B"], 10, sampler="leverage", storage="f32", eta=3.0, seed=w["seed"],
+            label="300^3 R10 B256 leverage")
+
+
+def test_full_120_4way_bf16():
+    w = ci.workload(3, dtype="bf16")
+    _replay(w, w["B"], 12, sampler="euclidean", storage="bf16", eta=1.5, seed=w["seed"],
+            label="120^4 R20 B512 bf16")
+
+
+def test_every_batch_member_f32():
+    specs = ci.batch_workload(count=64)
+    worst = 0.0
+    for i, s in enumerate(specs):
+        prob = ci.make_problem(s["dims"], s["R"], data_seed=s["data_seed"],
+                               init_seed=s["init_seed"], snr_db=s["snr_db"], dtype="bf16")
+        print(f"member {i} dims {s['dims']} R {s['R']}", flush=True)
+        worst = max(worst, _replay(prob, s["B"], 6, sampler="euclidean", storage="f32", eta=1.5,
+                                   seed=s["seed"], stream_id=s["stream_id"],
+                                   label=f"member {i}"))
+    print(f"worst {worst:.3e}")
