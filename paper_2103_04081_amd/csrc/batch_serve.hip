@@ -50,8 +50,10 @@ struct cpd_batch {
   std::vector<ChainDesc> descs;  // host mirror, by position
   ChainDesc* d_descs = nullptr;
   ChainState* d_states = nullptr;
+  int32_t* d_fitmap = nullptr;  // fit block table, by position
+  FitPlan fit{0, 0};
   std::vector<Group> groups;
-  int dtype = CPD_F32, max_I0 = 1, max_R = 1, fit_every = 25;
+  int dtype = CPD_F32, fit_every = 25;
   double wall_hz = 1e8;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -61,7 +63,7 @@ struct cpd_batch {
 namespace {
 
 struct BatchLayout {
-  size_t descs, states, total;
+  size_t descs, states, fitmap, total;
   std::vector<size_t> base;
 };
 
@@ -77,6 +79,8 @@ cpd_status plan_batch(const cpd_problem* ps, const cpd_options* os, int count,
   off = align_up(off + sizeof(ChainDesc) * count);
   L->states = off;
   off = align_up(off + sizeof(ChainState) * count);
+  L->fitmap = off;
+  off = align_up(off + sizeof(int32_t) * (count + 1));
   L->base.resize(count);
   for (int i = 0; i < count; ++i) {
     std::string why;
@@ -258,7 +262,7 @@ void destroy_batch(cpd_batch* b) {
 }
 
 hipError_t launch_fit_all(cpd_batch* b, hipStream_t stream) {
-  return launch_fit(b->d_descs, b->count, b->dtype, b->max_I0, b->max_R, true, stream);
+  return launch_fit(b->d_descs, b->d_fitmap, b->count, b->fit, b->dtype, true, stream);
 }
 
 cpd_status build_graph(cpd_batch* b) {
@@ -397,8 +401,6 @@ cpd_status cpd_batch_create(const cpd_problem* ps, const cpd_options* os, int32_
       Group& g = b->groups.back();
       g.count++;
       g.lds = std::max(g.lds, plans[i].lds);
-      b->max_I0 = std::max(b->max_I0, ps[i].dims[0]);
-      b->max_R = std::max(b->max_R, ps[i].R);
     }
     e = hipMemsetAsync(b->ws, 0, L.states + sizeof(ChainState) * count, b->stream);
     if (e != hipSuccess) return fail(hip_fail(e, "hipMemsetAsync"));
@@ -428,7 +430,13 @@ cpd_status cpd_batch_create(const cpd_problem* ps, const cpd_options* os, int32_
       s = restart_members(b, A0);
       if (s != CPD_OK) return fail(s);
     }
-    e = launch_fit(b->d_descs, count, b->dtype, b->max_I0, b->max_R, false, b->stream);
+    std::vector<int32_t> fitmap(count + 1);
+    b->fit = plan_fit(b->descs.data(), count, fitmap.data());
+    b->d_fitmap = (int32_t*)(b->ws + L.fitmap);
+    e = hipMemcpyAsync(b->d_fitmap, fitmap.data(), sizeof(int32_t) * (count + 1),
+                       hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpyAsync(fit table)"));
+    e = launch_fit(b->d_descs, b->d_fitmap, count, b->fit, b->dtype, false, b->stream);
     if (e != hipSuccess) return fail(hip_fail(e, "norm kernels"));
     s = read_states(b);
     if (s != CPD_OK) return fail(s);

@@ -73,6 +73,8 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
   off = align_up(off + sizeof(ChainDesc));
   w->parts = off;
   off = align_up(off + sizeof(double) * kFitParts);
+  w->fitmap = off;
+  off = align_up(off + 2 * sizeof(int32_t));
   for (int k = 0; k < p->N; ++k) {
     const size_t fb = sizeof(float) * (size_t)p->dims[k] * p->R;
     w->A[k] = off;
@@ -214,6 +216,8 @@ struct cpd_handle {
   ChainDesc desc;       // host mirror of the device descriptor
   ChainDesc* d_desc;    // in the workspace
   int32_t* d_mode;      // scratch int in the state block
+  int32_t* d_fitmap;    // fit block table (2 entries) in the workspace
+  FitPlan fit;
 };
 
 static cpd_status read_state(cpd_handle* h, ChainState* st) {
@@ -340,11 +344,16 @@ cpd_status cpd_init(const cpd_problem* p, const cpd_options* o, const void* X, i
       delete h;
       return s;
     }
+    int32_t fitmap[2];
+    h->fit = plan_fit(&h->desc, 1, fitmap);
+    h->d_fitmap = (int32_t*)(h->ws + w.fitmap);
+    e = hipMemcpyAsync(h->d_fitmap, fitmap, sizeof fitmap, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return fail(e, "hipMemcpyAsync(fit table)");
     StepArgs a{};
     a.op = OP_REFRESH;
     e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, w.lds, a, h->stream);
     if (e != hipSuccess) return fail(e, "refresh kernel");
-    e = launch_fit(h->d_desc, 1, o->storage, p->dims[0], p->R, false, h->stream);
+    e = launch_fit(h->d_desc, h->d_fitmap, 1, h->fit, o->storage, false, h->stream);
     if (e != hipSuccess) return fail(e, "norm kernels");
     s = device_status(h);
     if (s != CPD_OK) {
@@ -430,7 +439,7 @@ cpd_status cpd_fit(cpd_handle* h, double* fit) {
   }
   cpd_status s = set_device(h);
   if (s != CPD_OK) return s;
-  hipError_t e = launch_fit(h->d_desc, 1, h->o.storage, h->p.dims[0], h->p.R, true, h->stream);
+  hipError_t e = launch_fit(h->d_desc, h->d_fitmap, 1, h->fit, h->o.storage, true, h->stream);
   if (e != hipSuccess) return hip_fail(e, "fit kernels");
   ChainState st;
   s = read_state(h, &st);

@@ -23,6 +23,13 @@ constexpr int kChunkSteps = 32;         // MFMA K-steps (4 fibres each) per chun
 constexpr int kFibrePad = 4 * kChunkSteps;  // sampled fibres padded (zero weight) to full chunks
 constexpr double kRankTol = 1e-12;      // Cholesky pivot^2 <= tol * diagonal => rank deficient
 constexpr size_t kLdsBudget = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kFitRowsMin = 128;        // rows of copy 0 per fit block, at least
+constexpr size_t kFitLdsMax = 64 * 1024;  // A^(1) staged in LDS by the fit kernel up to this
+
+// Row stride (floats) of the transposed A^(1) the fit kernel stages in LDS:
+// a multiple of 64 columns plus 4, so the 16 rank columns of a 128-bit read
+// fall in distinct banks.
+__host__ __device__ inline int fit_a0_stride(int I0) { return (I0 + 63) / 64 * 64 + 4; }
 
 enum Op : int32_t { OP_STEP = 0, OP_SAMPLE = 1, OP_REPLAY = 2, OP_REFRESH = 3 };
 

@@ -13,12 +13,21 @@ hipError_t launch_chain_kernel(const ChainDesc* descs, int nchains, int rt, size
 hipError_t launch_layout_from_dense(const void* X, int in_dtype, const ChainDesc& d,
                                     hipStream_t stream);
 hipError_t launch_layout_from_copy0(const ChainDesc& d, hipStream_t stream);
-hipError_t launch_fit(const ChainDesc* d_descs, int nchains, int dtype, int max_I0, int max_R,
-                      bool inner, hipStream_t stream);
+// Fit work split over a set of decompositions: start[c] = first block of
+// decomposition c (start has nchains + 1 entries), lds = dynamic LDS of the
+// inner pass.
+struct FitPlan {
+  int32_t total_blocks;
+  size_t lds;
+};
+FitPlan plan_fit(const ChainDesc* host_descs, int nchains, int32_t* start);
+// d_start: device copy of the start table of plan_fit.
+hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_start, int nchains,
+                      const FitPlan& fp, int dtype, bool inner, hipStream_t stream);
 
 // Offsets of every region of one decomposition's workspace.
 struct WsPlan {
-  size_t state, desc, parts;
+  size_t state, desc, parts, fitmap;
   size_t A[kMaxModes], S[kMaxModes], C[kMaxModes];
   size_t X[kMaxModes];
   int32_t ld[kMaxModes];

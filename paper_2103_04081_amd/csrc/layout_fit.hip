@@ -11,7 +11,7 @@
 // with ||[[A]]||^2 = 1^T (hadamard_k A^(k)T A^(k)) 1 in FP64 and
 // <X, [[A]]> = sum_j sum_i x_j(i) (A^(1)(i,:) . z_j) streamed over copy 0
 // (z_j the KRP row of the fibre's multi-index), FP64 accumulation.
-#include "cpd_internal.hpp"
+#include "cpd_runtime.hpp"
 
 namespace cpdmi {
 
@@ -135,83 +135,209 @@ hipError_t launch_layout_from_copy0(const ChainDesc& d, hipStream_t stream) {
 }
 
 // ---------------------------------------------------------------------------
-// Fit: partial sums over the rows of copy 0.  mode 0: sum x^2; mode 1:
-// sum_j sum_i x_j(i) * (A^(0)(i,:) . z_j).  One partial per block.
+// Fit, partial pass over copy 0 (row j = the mode-1 fibre j, I0 elements).
+//   norm pass:  sum_j sum_i x_j(i)^2
+//   inner pass: sum_j sum_r z_j(r) y_j(r),  y_j = x_j A^(1)  (1 x R),
+//               z_j(r) = prod_{k>0} A^(k)(i_k(j), r)
+// Each block owns a contiguous range of rows; its four waves take 16-row
+// tiles in turn.  y for a tile is a 16 x I0 by I0 x R product on
+// v_mfma_f32_16x16x4f32 (the tensor's BF16 or FP32 values as the A
+// operand, A^(1) in FP32 as the B operand, FP32 accumulation), with A^(1)
+// staged transposed in LDS when it fits.  Per-tile sums are accumulated in
+// FP64.  Which block serves which decomposition comes from a prefix table
+// (start[c] = first block of decomposition c), so one launch covers a batch.
 // ---------------------------------------------------------------------------
-template <typename T, bool INNER>
-__global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc* __restrict__ descs,
-                                                                int nparts_per_chain, int a0_in_lds) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[kFitBlock / 64];
-  const ChainDesc* dp = descs + blockIdx.y;
-  if (!dp->active || (INNER && dp->state->done)) return;
-  const int N = dp->N, R = dp->R, I0 = dp->dims[0], ld0 = dp->ld[0];
-  const T* X0 = (const T*)dp->X[0];
-  // A^(1) rows: staged in LDS when they fit, else read through the caches
-  const float* A0s = a0_in_lds ? (const float*)smem : dp->A[0];
-  if (INNER && a0_in_lds) {
-    float* dst = (float*)smem;
-    for (int e = threadIdx.x; e < I0 * R; e += blockDim.x) dst[e] = dp->A[0][e];
-    __syncthreads();
-  }
-  int64_t rows = 1;
-  for (int k = 1; k < N; ++k) rows *= dp->dims[k];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wpb = kFitBlock / 64;
-  const int64_t gw = (int64_t)blockIdx.x * wpb + wave, nw = (int64_t)nparts_per_chain * wpb;
-  double acc = 0.0;
-  for (int64_t j = gw; j < rows; j += nw) {
-    const T* xr = X0 + j * ld0;
-    if (!INNER) {
-      for (int i = lane; i < I0; i += 64) {
-        const double x = (double)load_as_f32(xr, i);
-        acc += x * x;
-      }
-    } else {
-      // z_j(r) for r = lane (lanes >= R idle); R <= 64
-      float z = 0.f;
-      if (lane < R) {
-        int64_t rem = j;
-        z = 1.f;
-        for (int k = 1; k < N; ++k) {
-          const int ik = (int)(rem % dp->dims[k]);
-          rem /= dp->dims[k];
-          z *= dp->A[k][(int64_t)ik * R + lane];
-        }
-      }
-      for (int i0 = 0; i0 < I0; i0 += 64) {
-        const int i = i0 + lane;
-        float v = 0.f;
-        for (int r = 0; r < R; ++r) {
-          const float zr = __shfl(z, r);
-          if (i < I0) v = fmaf(A0s[i * R + r], zr, v);
-        }
-        if (i < I0) acc += (double)load_as_f32(xr, i) * (double)v;
-      }
-    }
-  }
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t w4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ void unpack16(const w4& v, float* x);
+template <>
+__device__ __forceinline__ void unpack16<float>(const w4& v, float* x) {
+  x[0] = __uint_as_float(v[0]);
+  x[1] = __uint_as_float(v[1]);
+  x[2] = __uint_as_float(v[2]);
+  x[3] = __uint_as_float(v[3]);
+}
+template <>
+__device__ __forceinline__ void unpack16<uint16_t>(const w4& v, float* x) {
+  const uint32_t w[4] = {v[0], v[1], v[2], v[3]};
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if (lane == 0) red[wave] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < wpb; ++w) s += red[w];
-    dp->parts[blockIdx.x] = s;
+  for (int q = 0; q < 4; ++q) {
+    x[2 * q] = __uint_as_float(w[q] << 16);
+    x[2 * q + 1] = __uint_as_float(w[q] & 0xFFFF0000u);
   }
 }
 
-// Final reduction (one block per chain).  mode 0: state->x2 = sum of parts.
-// mode 1: inner product, ||[[A]]||^2 from the Grams, and the fit.
+__device__ __forceinline__ int fit_chain_of(const int32_t* start, int nchains, int bid) {
+  int lo = 0, hi = nchains;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= bid) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T, bool INNER>
+__global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc* __restrict__ descs,
+                                                                const int32_t* __restrict__ start,
+                                                                int nchains, int lds_floats) {
+  extern __shared__ __align__(16) float a0t[];
+  __shared__ double red[kFitBlock / 64];
+  constexpr int E = 16 / (int)sizeof(T);  // elements per 16-byte load
+  constexpr int U = 64 / (4 * E);         // loads per lane per 64 columns
+  constexpr int Q = 4 * (int)sizeof(T);   // 16-byte words per 64 columns
+  const int c = fit_chain_of(start, nchains, blockIdx.x);
+  const ChainDesc* dp = descs + c;
+  if (!dp->active || (INNER && dp->state->done)) return;
+  const int b = blockIdx.x - start[c], nb = start[c + 1] - start[c];
+  const int N = dp->N, R = dp->R, I0 = dp->dims[0], ld0 = dp->ld[0];
+  int64_t J0 = 1;
+  for (int k = 1; k < N; ++k) J0 *= dp->dims[k];
+  const int64_t rpb = ((J0 + nb - 1) / nb + 15) / 16 * 16;
+  const int64_t r0 = (int64_t)b * rpb;
+  const int64_t r1 = r0 + rpb < J0 ? r0 + rpb : J0;
+  const int RT = (R + 15) / 16;
+  const int P = fit_a0_stride(I0);
+  const bool in_lds = INNER && 16 * RT * P <= lds_floats;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rq = lane & 15, kg = lane >> 4;
+  const CPD_GLOBAL float* A0 = gmem((const float*)dp->A[0]);
+  if (in_lds) {
+    for (int e = tid; e < 16 * RT * P; e += kFitBlock) a0t[e] = 0.f;
+    __syncthreads();
+    for (int e = tid; e < I0 * R; e += kFitBlock) {
+      const int i = e / R, col = e - i * R;
+      a0t[col * P + i] = A0[e];
+    }
+    __syncthreads();
+  }
+  const int nit = (I0 + 63) / 64;
+  const CPD_GLOBAL char* X0 = gmem((const char*)dp->X[0]);
+  double accd = 0.0;
+  for (int64_t t0 = r0 + 16 * wave; t0 < r1; t0 += 16 * (kFitBlock / 64)) {
+    const int64_t jr = t0 + rq < J0 ? t0 + rq : J0 - 1;  // rows past the end: any valid row
+    const CPD_GLOBAL w4* xr = (const CPD_GLOBAL w4*)(X0 + jr * (int64_t)ld0 * sizeof(T));
+    if (!INNER) {
+      const bool row_ok = t0 + rq < r1;
+      for (int it = 0; it < nit; ++it) {
+        w4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = xr[it * Q + 4 * u + kg];
+        float sq = 0.f;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          float x[E];
+          unpack16<T>(v[u], x);
+#pragma unroll
+          for (int s2 = 0; s2 < E; ++s2) sq = fmaf(x[s2], x[s2], sq);
+        }
+        if (row_ok) accd += (double)sq;
+      }
+      continue;
+    }
+    f4 acc[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) acc[rt] = f4{0.f, 0.f, 0.f, 0.f};
+    auto compute = [&](const w4 (&v)[U], int it) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float x[E];
+        unpack16<T>(v[u], x);
+        const int ib = 64 * it + (4 * u + kg) * E;  // column of x[0]
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          if (rt < RT) {
+            const int col = 16 * rt + rq;
+#pragma unroll
+            for (int s4 = 0; s4 < E / 4; ++s4) {
+              f4 bv;
+              if (in_lds) {
+                bv = *(const f4*)(a0t + col * P + ib + 4 * s4);
+              } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                  const int i = ib + 4 * s4 + s;
+                  bv[s] = (i < I0 && col < R) ? A0[(int64_t)i * R + col] : 0.f;
+                }
+              }
+#pragma unroll
+              for (int s = 0; s < 4; ++s)
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[4 * s4 + s], bv[s], acc[rt], 0, 0, 0);
+            }
+          }
+        }
+      }
+    };
+    w4 va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) va[u] = xr[4 * u + kg];
+    for (int it = 0; it < nit; it += 2) {
+      if (it + 1 < nit) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) vb[u] = xr[(it + 1) * Q + 4 * u + kg];
+      }
+      compute(va, it);
+      if (it + 2 < nit) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) va[u] = xr[(it + 2) * Q + 4 * u + kg];
+      }
+      if (it + 1 < nit) compute(vb, it + 1);
+    }
+    // lane holds y(row 4 kg + q, column 16 rt + rq)
+    float part = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = t0 + 4 * kg + q;
+      if (j < r1) {
+        float z[4] = {1.f, 1.f, 1.f, 1.f};
+        int64_t rem = j;
+        for (int k = 1; k < N; ++k) {
+          const int Ik = dp->dims[k];
+          const int64_t nxt = rem / Ik;
+          const int ik = (int)(rem - nxt * Ik);
+          rem = nxt;
+          const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]) + (int64_t)ik * R;
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            const int col = 16 * rt + rq;
+            if (rt < RT) z[rt] *= col < R ? Ak[col] : 0.f;
+          }
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+          if (rt < RT) part = fmaf(z[rt], acc[rt][q], part);
+      }
+    }
+    accd += (double)part;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) accd += __shfl_xor(accd, o);
+  if (lane == 0) red[wave] = accd;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < kFitBlock / 64; ++w) sum += red[w];
+    dp->parts[b] = sum;
+  }
+}
+
+// Final reduction, one block per decomposition.  Norm pass: state->x2.
+// Inner pass: <X, [[A]]>, ||[[A]]||^2 from the Gram matrices (FP64, rows
+// split over threads, combined in a fixed order) and the fit.
 template <bool INNER>
 __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __restrict__ descs,
-                                                         int nparts_per_chain) {
+                                                         const int32_t* __restrict__ start) {
   __shared__ double red[16];
+  __shared__ double had[kMaxRank * kMaxRank];
+  __shared__ double slice[1024];
   const ChainDesc* dp = descs + blockIdx.x;
   if (!dp->active || (INNER && dp->state->done)) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = start[blockIdx.x + 1] - start[blockIdx.x];
   double s = 0.0;
-  for (int p = threadIdx.x; p < nparts_per_chain; p += blockDim.x) s += dp->parts[p];
+  for (int p = tid; p < nb; p += blockDim.x) s += dp->parts[p];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if (lane == 0) red[wave] = s;
@@ -220,28 +346,49 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
   for (int w = 0; w < (int)(blockDim.x / 64); ++w) total += red[w];
   __syncthreads();
   if (!INNER) {
-    if (threadIdx.x == 0) dp->state->x2 = total;
+    if (tid == 0) dp->state->x2 = total;
     return;
   }
-  // ||[[A]]||^2 = sum_{r,s} prod_k (A^(k)T A^(k))_{rs}
-  const int R = dp->R, N = dp->N;
-  double h = 0.0;
-  for (int pr = threadIdx.x; pr < R * R; pr += blockDim.x) {
-    const int r = pr / R, c = pr - r * R;
-    double prod = 1.0;
-    for (int k = 0; k < N; ++k) {
-      const float* A = dp->A[k];
-      double g = 0.0;
-      for (int i = 0; i < dp->dims[k]; ++i) g += (double)A[(int64_t)i * R + r] * (double)A[(int64_t)i * R + c];
-      prod *= g;
+  // ||[[A]]||^2 = sum_{r,c} prod_k (A^(k)T A^(k))_{rc}
+  const int R = dp->R, N = dp->N, R2 = R * R;
+  const int slices = R2 >= 1024 ? 1 : 1024 / R2;
+  for (int p = tid; p < R2; p += blockDim.x) had[p] = 1.0;
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    const CPD_GLOBAL float* A = gmem((const float*)dp->A[k]);
+    const int Ik = dp->dims[k];
+    if (slices == 1) {
+      for (int p = tid; p < R2; p += blockDim.x) {
+        const int r = p / R, cc = p - r * R;
+        double g = 0.0;
+        for (int i = 0; i < Ik; ++i) g += (double)A[(int64_t)i * R + r] * (double)A[(int64_t)i * R + cc];
+        had[p] *= g;
+      }
+    } else {
+      const int p = tid % R2, sl = tid / R2;
+      if (sl < slices) {
+        const int r = p / R, cc = p - r * R;
+        double g = 0.0;
+        for (int i = sl; i < Ik; i += slices)
+          g += (double)A[(int64_t)i * R + r] * (double)A[(int64_t)i * R + cc];
+        slice[sl * R2 + p] = g;
+      }
+      __syncthreads();
+      if (tid < R2) {
+        double g = 0.0;
+        for (int q = 0; q < slices; ++q) g += slice[q * R2 + tid];
+        had[tid] *= g;
+      }
     }
-    h += prod;
+    __syncthreads();
   }
+  double h = 0.0;
+  for (int p = tid; p < R2; p += blockDim.x) h += had[p];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o);
   if (lane == 0) red[wave] = h;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     double xh = 0.0;
     for (int w = 0; w < (int)(blockDim.x / 64); ++w) xh += red[w];
     ChainState* st = dp->state;
@@ -257,13 +404,28 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
   }
 }
 
-constexpr size_t kFitLdsMax = 64 * 1024;
+FitPlan plan_fit(const ChainDesc* descs, int nchains, int32_t* start) {
+  FitPlan fp{0, 0};
+  int32_t acc = 0;
+  for (int c = 0; c < nchains; ++c) {
+    const ChainDesc& d = descs[c];
+    start[c] = acc;
+    int64_t J0 = 1;
+    for (int k = 1; k < d.N; ++k) J0 *= d.dims[k];
+    int64_t nb = (J0 + kFitRowsMin - 1) / kFitRowsMin;
+    if (nb < 1) nb = 1;
+    if (nb > kFitParts) nb = kFitParts;
+    acc += (int32_t)nb;
+    const size_t need = sizeof(float) * 16 * (size_t)((d.R + 15) / 16) * fit_a0_stride(d.dims[0]);
+    if (need <= kFitLdsMax && need > fp.lds) fp.lds = need;
+  }
+  start[nchains] = acc;
+  fp.total_blocks = acc;
+  return fp;
+}
 
-hipError_t launch_fit(const ChainDesc* d_descs, int nchains, int dtype, int max_I0, int max_R,
-                      bool inner, hipStream_t stream) {
-  const size_t need = sizeof(float) * (size_t)max_I0 * max_R;
-  const int in_lds = inner && need <= kFitLdsMax;
-  const size_t lds = in_lds ? need : 0;
+hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_start, int nchains,
+                      const FitPlan& fp, int dtype, bool inner, hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)fit_partial_kernel<float, true>,
@@ -274,30 +436,32 @@ hipError_t launch_fit(const ChainDesc* d_descs, int nchains, int dtype, int max_
     if (e != hipSuccess) return e;
     attr = true;
   }
-  dim3 grid(kFitParts, nchains);
+  const dim3 grid((unsigned)fp.total_blocks);
+  const size_t lds = inner ? fp.lds : 0;
+  const int lds_floats = (int)(lds / sizeof(float));
   if (dtype == CPD_BF16) {
     if (inner)
       hipLaunchKernelGGL((fit_partial_kernel<uint16_t, true>), grid, dim3(kFitBlock), lds, stream,
-                         d_descs, kFitParts, in_lds);
+                         d_descs, d_start, nchains, lds_floats);
     else
       hipLaunchKernelGGL((fit_partial_kernel<uint16_t, false>), grid, dim3(kFitBlock), 0, stream,
-                         d_descs, kFitParts, 0);
+                         d_descs, d_start, nchains, 0);
   } else {
     if (inner)
       hipLaunchKernelGGL((fit_partial_kernel<float, true>), grid, dim3(kFitBlock), lds, stream,
-                         d_descs, kFitParts, in_lds);
+                         d_descs, d_start, nchains, lds_floats);
     else
       hipLaunchKernelGGL((fit_partial_kernel<float, false>), grid, dim3(kFitBlock), 0, stream,
-                         d_descs, kFitParts, 0);
+                         d_descs, d_start, nchains, 0);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (inner)
     hipLaunchKernelGGL((fit_final_kernel<true>), dim3(nchains), dim3(1024), 0, stream, d_descs,
-                       kFitParts);
+                       d_start);
   else
     hipLaunchKernelGGL((fit_final_kernel<false>), dim3(nchains), dim3(1024), 0, stream, d_descs,
-                       kFitParts);
+                       d_start);
   return hipGetLastError();
 }
 

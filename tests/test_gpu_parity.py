@@ -192,10 +192,20 @@ def test_nonneg_projection():
     dec.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_fit_matches_explicit_reconstruction(storage):
-    _announce("fit", storage)
-    prob = problem((37, 45, 53), 7, storage=storage)
+FIT_CASES = [
+    ((37, 45, 53), 7, "f32"),
+    ((37, 45, 53), 7, "bf16"),
+    ((130, 21, 19), 33, "f32"),     # three rank tiles, ragged 64-column tail
+    ((520, 9, 8), 20, "bf16"),      # A^(1) too large for LDS: read from global
+    ((9, 7, 6, 5), 3, "f32"),       # 4-way, short fibres
+    ((1, 40, 30), 2, "f32"),        # fibres of length one
+]
+
+
+@pytest.mark.parametrize("dims,R,storage", FIT_CASES)
+def test_fit_matches_explicit_reconstruction(dims, R, storage):
+    _announce("fit", dims, R, storage)
+    prob = problem(dims, R, storage=storage)
     dec = gpu_decomposition(prob, 30, storage=storage, eta=0.3)
     f0 = dec.fit()
     assert math.isclose(f0, O.fit_explicit(prob["X"], prob["A0"]), rel_tol=1e-6, abs_tol=1e-6)
