@@ -162,29 +162,55 @@ cpd_status init_member(const cpd_problem* p, const cpd_options* o, const void* X
     if (e != hipSuccess) return hip_fail(e, "layout kernels");
     return CPD_OK;
   }
-  // host input: round to the storage type on the host, copy 0 by rows
-  const int I0 = p->dims[0];
-  const int64_t rows = w.rows[0];
+  // host input: rounded to the storage type on the host into two pinned
+  // chunks (alternating, so conversion overlaps the copy of the previous
+  // chunk), copied densely into the region of copy 1 (it holds at least
+  // prod(dims) elements and is rebuilt afterwards), then spread into the
+  // padded rows of copy 0 on the device and transposed into copies 1..N-1.
+  const int64_t total = w.rows[0] * p->dims[0];
   const size_t es = o->storage == CPD_BF16 ? 2 : 4;
-  const int64_t chunk = std::max<int64_t>(1, ((int64_t)8 << 20) / ((int64_t)I0 * es));
-  std::vector<unsigned char> buf((size_t)std::min(chunk, rows) * I0 * es);
-  for (int64_t r0 = 0; r0 < rows; r0 += chunk) {
-    const int64_t nr = std::min(chunk, rows - r0);
-    const int64_t b0 = r0 * I0, cnt = nr * I0;
-    for (int64_t i = 0; i < cnt; ++i) {
-      const float v = x_dtype == CPD_F64 ? (float)((const double*)X)[b0 + i]
-                                         : ((const float*)X)[b0 + i];
-      if (es == 2) ((uint16_t*)buf.data())[i] = f32_to_bf16_rne(v);
-      else ((float*)buf.data())[i] = v;
+  const int64_t chunk = ((int64_t)8 << 20) / (int64_t)es;  // elements per chunk
+  void* hb[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  auto release = [&]() {
+    for (int q = 0; q < 2; ++q) {
+      if (ev[q]) (void)hipEventDestroy(ev[q]);
+      if (hb[q]) (void)hipHostFree(hb[q]);
     }
-    e = hipMemcpy2DAsync((char*)desc->X[0] + (size_t)r0 * w.ld[0] * es, (size_t)w.ld[0] * es,
-                         buf.data(), (size_t)I0 * es, (size_t)I0 * es, (size_t)nr,
-                         hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync(X)");
-    // the staging buffer is reused by the next chunk
-    e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  };
+  for (int q = 0; q < 2; ++q) {
+    e = hipHostMalloc(&hb[q], (size_t)chunk * es, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(stream);
+      release();
+      return hip_fail(e, "pinned staging");
+    }
   }
+  char* staged = (char*)desc->X[1];
+  int q = 0;
+  for (int64_t e0 = 0; e0 < total; e0 += chunk, q ^= 1) {
+    const int64_t cnt = std::min(chunk, total - e0);
+    e = hipEventSynchronize(ev[q]);  // the copy that last read this chunk is done
+    if (e != hipSuccess) break;
+    for (int64_t i = 0; i < cnt; ++i) {
+      const float v = x_dtype == CPD_F64 ? (float)((const double*)X)[e0 + i]
+                                         : ((const float*)X)[e0 + i];
+      if (es == 2) ((uint16_t*)hb[q])[i] = f32_to_bf16_rne(v);
+      else ((float*)hb[q])[i] = v;
+    }
+    e = hipMemcpyAsync(staged + (size_t)e0 * es, hb[q], (size_t)cnt * es, hipMemcpyHostToDevice,
+                       stream);
+    if (e != hipSuccess) break;
+    e = hipEventRecord(ev[q], stream);
+    if (e != hipSuccess) break;
+  }
+  hipError_t es2 = hipStreamSynchronize(stream);
+  release();
+  if (e != hipSuccess) return hip_fail(e, "staging copy of X");
+  if (es2 != hipSuccess) return hip_fail(es2, "hipStreamSynchronize");
+  e = launch_copy0_from_staged(staged, *desc, stream);
+  if (e != hipSuccess) return hip_fail(e, "layout kernels");
   e = launch_layout_from_copy0(*desc, stream);
   if (e != hipSuccess) return hip_fail(e, "layout kernels");
   return CPD_OK;

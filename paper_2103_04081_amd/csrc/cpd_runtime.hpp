@@ -13,6 +13,7 @@ hipError_t launch_chain_kernel(const ChainDesc* descs, int nchains, int rt, size
 hipError_t launch_layout_from_dense(const void* X, int in_dtype, const ChainDesc& d,
                                     hipStream_t stream);
 hipError_t launch_layout_from_copy0(const ChainDesc& d, hipStream_t stream);
+hipError_t launch_copy0_from_staged(const void* staged, const ChainDesc& d, hipStream_t stream);
 // Fit work split over a set of decompositions: start[c] = first block of
 // decomposition c (start has nchains + 1 entries), lds = dynamic LDS of the
 // inner pass.

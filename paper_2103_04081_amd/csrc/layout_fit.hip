@@ -127,6 +127,23 @@ hipError_t launch_layout_from_dense(const void* X, int in_dtype, const ChainDesc
   return layout_all<float, float>((const float*)X, false, d, 0, stream);
 }
 
+// Copy 0 from the dense tensor already in the storage type (staged on the
+// device without row padding).
+hipError_t launch_copy0_from_staged(const void* staged, const ChainDesc& d, hipStream_t stream) {
+  int64_t total = 1;
+  for (int k = 0; k < d.N; ++k) total *= d.dims[k];
+  const int I0 = d.dims[0];
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (d.dtype == CPD_BF16)
+    hipLaunchKernelGGL((layout_copy0<uint16_t, uint16_t>), dim3((unsigned)blocks), dim3(256), 0,
+                       stream, (const uint16_t*)staged, (uint16_t*)d.X[0], I0, total / I0, d.ld[0]);
+  else
+    hipLaunchKernelGGL((layout_copy0<float, float>), dim3((unsigned)blocks), dim3(256), 0, stream,
+                       (const float*)staged, (float*)d.X[0], I0, total / I0, d.ld[0]);
+  return hipGetLastError();
+}
+
 // Build copies 1..N-1 from copy 0 (already in storage type).
 hipError_t launch_layout_from_copy0(const ChainDesc& d, hipStream_t stream) {
   if (d.dtype == CPD_BF16)
