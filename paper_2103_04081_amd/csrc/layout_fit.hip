@@ -366,35 +366,53 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
     if (tid == 0) dp->state->x2 = total;
     return;
   }
-  // ||[[A]]||^2 = sum_{r,c} prod_k (A^(k)T A^(k))_{rc}
+  // ||[[A]]||^2 = sum_{r,c} prod_k (A^(k)T A^(k))_{rc}.  Factor rows pass
+  // through LDS in chunks; thread (pair p, slice sl) sums rows sl, sl +
+  // slices, ... of the chunk for its pair in FP64; slices combine in order.
   const int R = dp->R, N = dp->N, R2 = R * R;
   const int slices = R2 >= 1024 ? 1 : 1024 / R2;
+  constexpr int kRows = 64;
+  __shared__ float rows[kRows * kMaxRank];
   for (int p = tid; p < R2; p += blockDim.x) had[p] = 1.0;
-  __syncthreads();
   for (int k = 0; k < N; ++k) {
     const CPD_GLOBAL float* A = gmem((const float*)dp->A[k]);
     const int Ik = dp->dims[k];
+    double g[4] = {0.0, 0.0, 0.0, 0.0};  // pairs tid, tid + 1024, ... (slices == 1)
+    double gs = 0.0;                     // pair tid % R2, slice tid / R2
+    for (int i0 = 0; i0 < Ik; i0 += kRows) {
+      const int nr = Ik - i0 < kRows ? Ik - i0 : kRows;
+      __syncthreads();
+      for (int e = tid; e < nr * R; e += blockDim.x) rows[e] = A[(int64_t)i0 * R + e];
+      __syncthreads();
+      if (slices == 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int p = tid + q * 1024;
+          if (p < R2) {
+            const int r = p / R, cc = p - r * R;
+            for (int i = 0; i < nr; ++i) g[q] += (double)rows[i * R + r] * (double)rows[i * R + cc];
+          }
+        }
+      } else {
+        const int p = tid % R2, sl = tid / R2;
+        if (sl < slices) {
+          const int r = p / R, cc = p - r * R;
+          for (int i = sl; i < nr; i += slices) gs += (double)rows[i * R + r] * (double)rows[i * R + cc];
+        }
+      }
+    }
+    __syncthreads();
     if (slices == 1) {
-      for (int p = tid; p < R2; p += blockDim.x) {
-        const int r = p / R, cc = p - r * R;
-        double g = 0.0;
-        for (int i = 0; i < Ik; ++i) g += (double)A[(int64_t)i * R + r] * (double)A[(int64_t)i * R + cc];
-        had[p] *= g;
-      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (tid + q * 1024 < R2) had[tid + q * 1024] *= g[q];
     } else {
-      const int p = tid % R2, sl = tid / R2;
-      if (sl < slices) {
-        const int r = p / R, cc = p - r * R;
-        double g = 0.0;
-        for (int i = sl; i < Ik; i += slices)
-          g += (double)A[(int64_t)i * R + r] * (double)A[(int64_t)i * R + cc];
-        slice[sl * R2 + p] = g;
-      }
+      if (tid / R2 < slices) slice[tid] = gs;
       __syncthreads();
       if (tid < R2) {
-        double g = 0.0;
-        for (int q = 0; q < slices; ++q) g += slice[q * R2 + tid];
-        had[tid] *= g;
+        double t = 0.0;
+        for (int q = 0; q < slices; ++q) t += slice[q * R2 + tid];
+        had[tid] *= t;
       }
     }
     __syncthreads();
