@@ -275,6 +275,84 @@ CPD_API cpd_status cpd_batch_read_factors(cpd_batch* b, int32_t i, int32_t n, fl
 /* Release the batch (the workspace stays the caller's). */
 CPD_API cpd_status cpd_batch_destroy(cpd_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.  Requests wait in a
+ * queue; a request is admitted as soon as a slot is free and its workspace
+ * (cpd_workspace_size bytes) fits in the free part of the server's arena.
+ * Admission (tensor layout, distributions) runs on its own stream while the
+ * admitted requests step, so newcomers join the running set at the next
+ * round; a round is round_steps steps of every admitted request followed by
+ * one fit check of all of them.  A request leaves when its fit reaches
+ * options.fit_target or its t reaches options.max_steps; its factors are
+ * copied out and its slot and arena space are reused.  Each request runs
+ * exactly the computation of a single handle stepped in rounds of
+ * round_steps with a fit check after each round, so its result does not
+ * depend on the other requests in the mix.
+ * ------------------------------------------------------------------------ */
+typedef struct cpd_server cpd_server;
+
+typedef struct cpd_server_config {
+  int32_t max_slots;        /* requests on the device at once, 1..4096 */
+  int32_t queue_capacity;   /* waiting requests beyond which cpd_submit refuses */
+  int32_t round_steps;      /* steps per round = steps between fit checks, >= 1 */
+  int32_t pad;
+} cpd_server_config;
+
+typedef struct cpd_request {
+  cpd_problem problem;
+  cpd_options options;            /* fit_every is ignored (round_steps applies) */
+  const void* X;                  /* dense tensor (layout as cpd_init) */
+  int32_t x_dtype;                /* CPD_F32 or CPD_F64 */
+  int32_t x_space;                /* CPD_HOST or CPD_DEVICE (current device) */
+  const float* A0[CPD_MAX_MODES]; /* initial factors, host */
+  float* out[CPD_MAX_MODES];      /* host buffers for the final factors (NULL: not copied) */
+} cpd_request;
+
+typedef struct cpd_result {
+  cpd_status status;          /* CPD_OK, or the request's error */
+  int32_t reached;            /* 1 if fit >= fit_target */
+  double fit;                 /* fit at the last check */
+  int64_t steps;              /* steps taken */
+  double seconds_queued;      /* submit -> admission started (host clock) */
+  double seconds_admit;       /* admission (layout, distributions) */
+  double seconds_to_fit;      /* first distributions -> stopping check (device clock) */
+  double seconds_total;       /* submit -> result available (host clock) */
+} cpd_result;
+
+/*
+ * cpd_server_create: start the request loop on the current device.  arena is
+ * caller-owned device memory (256-byte aligned) from which admitted requests
+ * get their workspaces; it must outlive the server.  stream is ignored (the
+ * server owns its streams).
+ */
+CPD_API cpd_status cpd_server_create(const cpd_server_config* cfg, void* arena, size_t arena_bytes,
+                                     cpd_server** out);
+
+/*
+ * cpd_submit: queue a request.  X, A0 and the out buffers must stay valid
+ * until cpd_poll reports a final status for the ticket.
+ * Errors: CPD_E_INVALID (bad problem), CPD_E_OOM (its workspace can never fit
+ * in the arena), CPD_E_QUEUE_FULL.
+ */
+CPD_API cpd_status cpd_submit(cpd_server* s, const cpd_request* r, uint64_t* ticket);
+
+/*
+ * cpd_poll: non-blocking.  CPD_PENDING while the request waits or runs;
+ * otherwise fills *out, forgets the ticket and returns CPD_OK.
+ * CPD_E_NOT_FOUND for an unknown (or already collected) ticket.
+ */
+CPD_API cpd_status cpd_poll(cpd_server* s, uint64_t ticket, cpd_result* out);
+
+/* Counters: requests waiting, running, finished and not yet collected. */
+CPD_API cpd_status cpd_server_stats(cpd_server* s, int32_t* waiting, int32_t* running,
+                                    int32_t* finished);
+
+/*
+ * cpd_server_destroy: stop the loop.  Running requests are abandoned;
+ * uncollected results are dropped.
+ */
+CPD_API cpd_status cpd_server_destroy(cpd_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,24 @@ class cpd_member_info(ctypes.Structure):
                 ("seconds_done", ctypes.c_double), ("ksplit", ctypes.c_int32 * MAX_MODES)]
 
 
+class cpd_server_config(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
+                ("round_steps", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class cpd_request(ctypes.Structure):
+    _fields_ = [("problem", cpd_problem), ("options", cpd_options), ("X", ctypes.c_void_p),
+                ("x_dtype", ctypes.c_int32), ("x_space", ctypes.c_int32),
+                ("A0", ctypes.c_void_p * MAX_MODES), ("out", ctypes.c_void_p * MAX_MODES)]
+
+
+class cpd_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reached", ctypes.c_int32), ("fit", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("seconds_queued", ctypes.c_double),
+                ("seconds_admit", ctypes.c_double), ("seconds_to_fit", ctypes.c_double),
+                ("seconds_total", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -120,6 +138,11 @@ def _extra_signatures(L):
         "cpd_batch_member_info": (st, [H, ctypes.c_int32, P(cpd_member_info)]),
         "cpd_batch_read_factors": (st, [H, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32]),
         "cpd_batch_destroy": (st, [H]),
+        "cpd_server_create": (st, [P(cpd_server_config), vp, ctypes.c_size_t, P(H)]),
+        "cpd_submit": (st, [H, P(cpd_request), P(ctypes.c_uint64)]),
+        "cpd_poll": (st, [H, ctypes.c_uint64, P(cpd_result)]),
+        "cpd_server_stats": (st, [H, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]),
+        "cpd_server_destroy": (st, [H]),
     }
     for name, (res, args) in extra.items():
         if hasattr(L, name):
@@ -300,6 +323,38 @@ def cpd_batch_read_factors(b, i, n, dst_ptr, space):
 
 def cpd_batch_destroy(b):
     return check(lib().cpd_batch_destroy(b), "cpd_batch_destroy")
+
+
+def cpd_server_create(max_slots, queue_capacity, round_steps, arena_ptr, arena_bytes):
+    cfg = cpd_server_config(int(max_slots), int(queue_capacity), int(round_steps), 0)
+    h = ctypes.c_void_p()
+    check(lib().cpd_server_create(ctypes.byref(cfg), ctypes.c_void_p(arena_ptr), arena_bytes,
+                                  ctypes.byref(h)), "cpd_server_create")
+    return h
+
+
+def cpd_submit(s, request):
+    t = ctypes.c_uint64()
+    check(lib().cpd_submit(s, ctypes.byref(request), ctypes.byref(t)), "cpd_submit")
+    return t.value
+
+
+def cpd_poll(s, ticket):
+    """None while pending, else the cpd_result."""
+    r = cpd_result()
+    st = check(lib().cpd_poll(s, int(ticket), ctypes.byref(r)), "cpd_poll")
+    return None if st == CPD_PENDING else r
+
+
+def cpd_server_stats(s):
+    w, r, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().cpd_server_stats(s, ctypes.byref(w), ctypes.byref(r), ctypes.byref(f)),
+          "cpd_server_stats")
+    return w.value, r.value, f.value
+
+
+def cpd_server_destroy(s):
+    return check(lib().cpd_server_destroy(s), "cpd_server_destroy")
 
 
 # --- convenience objects ----------------------------------------------------
@@ -486,6 +541,81 @@ class Decomposition:
         if getattr(self, "h", None) is not None:
             cpd_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A request server on one device with a torch-allocated arena.
+
+    ``submit`` takes a numpy tensor (host) or a CUDA torch tensor laid out
+    mode-1-fastest (shape dims[::-1], C-contiguous) plus the initial factors;
+    ``poll`` returns None while the request is pending, else a dict with the
+    result fields and the final factors.
+    """
+
+    def __init__(self, arena_bytes, *, max_slots=64, queue_capacity=4096, round_steps=25,
+                 device="cuda"):
+        self.device = torch.device(device)
+        self.arena, self.arena_ptr = _workspace(int(arena_bytes), self.device)
+        self.arena_bytes = int(arena_bytes)
+        self.round_steps = int(round_steps)
+        self.h = cpd_server_create(max_slots, queue_capacity, round_steps, self.arena_ptr,
+                                   self.arena_bytes)
+        self._keep = {}
+
+    def submit(self, X, A0, *, B, dims=None, seed=0, stream_id=0, sampler="euclidean",
+               rule="adagrad", eta=1.0, alpha=0.0, b=0.0, beta=0.0, gamma=1.0, storage="bf16",
+               nonneg=False, fit_target=0.99, max_steps=5000, ksplit=None):
+        if isinstance(X, torch.Tensor):
+            assert X.is_cuda and X.is_contiguous()
+            dims = list(dims) if dims is not None else list(X.shape[::-1])
+            x_ptr, x_space = X.data_ptr(), CPD_DEVICE
+            x_dtype = CPD_F64 if X.dtype == torch.float64 else CPD_F32
+            Xk = X
+        else:
+            Xk, x_dtype = _host_tensor(X)
+            dims = list(Xk.shape)
+            x_ptr, x_space = Xk.ctypes.data, CPD_HOST
+        A0 = [np.ascontiguousarray(np.asarray(a, dtype=np.float32)) for a in A0]
+        R = A0[0].shape[1]
+        out = [np.empty((I, R), dtype=np.float32) for I in dims]
+        req = cpd_request()
+        req.problem = make_problem(dims, R, B, seed, stream_id)
+        req.options = make_options(sampler, rule, alpha, eta, b, beta, gamma, storage, nonneg,
+                                   fit_every=self.round_steps, fit_target=fit_target,
+                                   max_steps=max_steps, ksplit=ksplit)
+        req.X = x_ptr
+        req.x_dtype, req.x_space = x_dtype, x_space
+        for k in range(len(dims)):
+            req.A0[k] = A0[k].ctypes.data
+            req.out[k] = out[k].ctypes.data
+        ticket = cpd_submit(self.h, req)
+        self._keep[ticket] = (Xk, A0, out)
+        return ticket
+
+    def poll(self, ticket):
+        r = cpd_poll(self.h, ticket)
+        if r is None:
+            return None
+        _, _, out = self._keep.pop(ticket)
+        return {"status": r.status, "reached": bool(r.reached), "fit": r.fit, "steps": r.steps,
+                "seconds_queued": r.seconds_queued, "seconds_admit": r.seconds_admit,
+                "seconds_to_fit": r.seconds_to_fit, "seconds_total": r.seconds_total,
+                "factors": out}
+
+    def stats(self):
+        return cpd_server_stats(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            cpd_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -28,7 +28,8 @@ def test_headers_declare_entry_points():
                  "cpd_workspace_size", "cpd_read_state", "cpd_write_state", "cpd_destroy",
                  "cpd_batch_workspace_size", "cpd_batch_create", "cpd_batch_step",
                  "cpd_batch_fits", "cpd_batch_run", "cpd_batch_member_info",
-                 "cpd_batch_destroy"):
+                 "cpd_batch_destroy", "cpd_server_create", "cpd_submit", "cpd_poll",
+                 "cpd_server_stats", "cpd_server_destroy"):
         assert must in names, must
 
 
