@@ -82,6 +82,10 @@ def parse():
     ap.add_argument("--no-seq", action="store_true",
                     help="skip the per-tensor FP32 comparison of the batched section")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving section (profiling)")
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MiB (a "
                          "known-size kernel to scale hardware byte counters)")
@@ -121,6 +125,11 @@ def main():
     torch.cuda.set_device(0)
     if args.batch_only:
         print(json.dumps({"batch": batch_bench(args.batch_count, seq=not args.no_seq)}),
+              flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serve": serve_bench(args.serve_requests),
+                          "serve_saturated": serve_bench(args.serve_requests, saturate=True)}),
               flush=True)
         return
     w = ci.workload(2)
@@ -165,6 +174,9 @@ def main():
         extra["time_to_fit"] = time_to_fit(make, target=0.99, every=25, max_steps=40000)
     if not args.no_batch:
         extra["batch"] = batch_bench(args.batch_count, seq=not args.no_seq)
+    if not args.no_serve:
+        extra["serve"] = serve_bench(args.serve_requests)
+        extra["serve_saturated"] = serve_bench(args.serve_requests, saturate=True)
 
     out = {
         "metric": METRIC,
@@ -285,6 +297,75 @@ def batch_bench(count=64, seq=True):
         "tune_and_create_seconds": create_s, "host_generation_seconds": gen_s,
         "per_tensor_fp32_sequential": seq,
         "speedup_vs_per_tensor_fp32": None if seq is None else seq["seconds"] / run_s,
+    }
+
+
+SERVE_ETA = 1.0
+
+
+def serve_bench(n_requests=200, rate=50.0, saturate=False):
+    """Poisson arrivals (50 req/s) of 3-way / 4-way BF16 requests into the
+    server, each run to fit 0.99 or 5000 steps.  Tensors are built on the
+    device before the clock starts (seeded recipe); the server stages them
+    (layout, BF16 rounding) at admission, inside the measured time."""
+    import numpy as np
+    import torch
+
+    import cpd_inputs as ci
+    import paper_2103_04081_amd as P
+    trace = ci.request_trace(n_requests, rate=rate)
+    t0 = time.perf_counter()
+    data = [ci.device_problem(r) for r in trace]
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    arena = 64 << 30
+    srv = P.Server(arena, max_slots=128, queue_capacity=4096, round_steps=25)
+    pending, done = {}, []
+    start = time.perf_counter()
+    nxt = 0
+    while nxt < len(trace) or pending:
+        now = time.perf_counter() - start
+        while nxt < len(trace) and (saturate or trace[nxt]["arrival"] <= now):
+            r = trace[nxt]
+            X, A0 = data[nxt]
+            tk = srv.submit(X, A0, B=r["B"], seed=r["seed"], stream_id=r["stream_id"],
+                            sampler="euclidean", eta=SERVE_ETA, storage="bf16",
+                            fit_target=0.99, max_steps=5000)
+            pending[tk] = (nxt, time.perf_counter() - start)
+            nxt += 1
+        for tk in list(pending):
+            res = srv.poll(tk)
+            if res is not None:
+                i, t_sub = pending.pop(tk)
+                res["arrival"] = t_sub
+                res["finish"] = time.perf_counter() - start
+                res["index"] = i
+                res.pop("factors")
+                done.append(res)
+        time.sleep(0.0005)
+    makespan = max(d["finish"] for d in done)
+    srv.close()
+    del data
+    ok = [d for d in done if d["status"] == 0]
+    reached = [d for d in ok if d["reached"]]
+    fit_t = np.array([d["seconds_admit"] + d["seconds_to_fit"] for d in reached])
+    tot_t = np.array([d["seconds_total"] for d in reached])
+    pct = lambda a, q: float(np.percentile(a, q)) if len(a) else None  # noqa: E731
+    return {
+        "workload": f"{n_requests} requests, Poisson arrivals at {rate:g}/s"
+                    f"{' (all submitted at once)' if saturate else ''}; 50/50 3-way dims "
+                    "U{64..512} and 4-way dims U{32..128}, R U{8..32}, B 128, BF16 storage, "
+                    f"SNR 30 dB; Euclidean sampler, AdaGrad eta={SERVE_ETA}; fit check every 25 "
+                    "steps; each to fit 0.99 or 5000 steps",
+        "solves_per_s": len(reached) / makespan, "completed": len(done), "reached": len(reached),
+        "errors": len(done) - len(ok), "makespan_s": makespan,
+        "time_to_fit_from_admission_p50": pct(fit_t, 50),
+        "time_to_fit_from_admission_p99": pct(fit_t, 99),
+        "time_to_fit_from_arrival_p50": pct(tot_t, 50),
+        "time_to_fit_from_arrival_p99": pct(tot_t, 99),
+        "queued_p99": pct(np.array([d["seconds_queued"] for d in done]), 99),
+        "steps_p50": pct(np.array([d["steps"] for d in done]), 50),
+        "device_generation_seconds": gen_s,
     }
 
 

@@ -36,6 +36,7 @@ __all__ = [
     "batch_workload",
     "request_trace",
     "round_bf16",
+    "device_problem",
 ]
 
 
@@ -223,3 +224,37 @@ def request_trace(count, *, rate=50.0, seed=1005, B=128, snr_db=30.0, dtype="bf1
                         init_seed=seed * 1000 + 500 + i, snr_db=snr_db, dtype=dtype,
                         seed=3005, stream_id=i))
     return out
+
+
+def device_problem(spec, device="cuda"):
+    """The recipe of :func:`make_problem` (Gaussian factors, no skew) with the
+    tensor formed on the device, for workloads too large to build on the host
+    at their arrival rate.
+
+    The true factors and the initial factors come from PCG64 on the host as in
+    :func:`make_problem`; X_true = [[A]] is one FP32 GEMM on the device and
+    the noise comes from torch's device generator seeded with the data seed.
+    Returns (X, A0) with X a C-contiguous FP32 device tensor of shape
+    dims[::-1] (mode 1 fastest in memory).
+    """
+    import torch
+
+    dims, R = [int(d) for d in spec["dims"]], int(spec["R"])
+    rng = rng_for(spec["data_seed"])
+    A = gaussian_factors(dims, R, rng)
+    A0 = init_factors(dims, R, spec["init_seed"])
+    F = [torch.as_tensor(a, dtype=torch.float32, device=device) for a in A]
+    # rows of T enumerate (i_2, ..., i_N) with i_2 fastest
+    T = F[1]
+    for a in F[2:]:
+        T = (a[:, None, :] * T[None, :, :]).reshape(-1, R)
+    X = T @ F[0].T  # (J_1, I_1) row-major: i_1 fastest in memory
+    if spec.get("snr_db") is not None:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(spec["data_seed"]))
+        Nz = torch.randn(X.shape, generator=g, device=device, dtype=torch.float32)
+        sigma = torch.linalg.vector_norm(X) / (torch.linalg.vector_norm(Nz)
+                                               * 10.0 ** (spec["snr_db"] / 20.0))
+        X.add_(Nz, alpha=float(sigma))
+        del Nz
+    return X.reshape(dims[::-1]).contiguous(), A0
