@@ -117,6 +117,7 @@ void fill_desc(const cpd_problem* p, const cpd_options* o, const WsPlan& w, char
     d->dims[k] = p->dims[k];
     d->ld[k] = w.ld[k];
     d->ksplit[k] = o->ksplit[k] > 0 ? o->ksplit[k] : host_ksplit(p->dims[k], o->storage, p->B, p->R);
+    d->vw[k] = host_vw(p->dims[k], o->storage);
     d->X[k] = base + w.X[k];
     d->A[k] = (float*)(base + w.A[k]);
     d->S[k] = (float*)(base + w.S[k]);

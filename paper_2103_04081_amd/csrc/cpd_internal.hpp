@@ -56,6 +56,7 @@ struct ChainDesc {
   int32_t dims[kMaxModes];
   int32_t ld[kMaxModes];               // row stride (elements) of copy n
   int32_t ksplit[kMaxModes];           // K-split of the contraction per mode
+  int32_t vw[kMaxModes];               // output rows per lane in the contraction (1 or 2)
   int32_t dtype;                       // CPD_F32 or CPD_BF16 storage
   int32_t sampler, rule, nonneg;
   float alpha, eta, b;
@@ -169,8 +170,17 @@ __host__ __device__ inline float bf16_to_f32(uint16_t h) {
 // Largest K-split of mode n's contraction the step kernel supports: every
 // (row tile, K part) pair needs its own wave, and every part at least one
 // chunk of fibres.
+// Output rows per lane in the contraction of a mode of size In (a tile
+// covers 16 * vw rows): BF16 reads element pairs, FP32 single elements
+// (pairs of FP32 rows halve the tile count and unbalance the waves at the
+// mode sizes of interest).
+inline int host_vw(int In, int dtype) {
+  (void)In;
+  return dtype == CPD_BF16 ? 2 : 1;
+}
+
 inline int max_ksplit(int In, int dtype, int B, int R) {
-  const int vw = dtype == CPD_BF16 ? 2 : 1;
+  const int vw = host_vw(In, dtype);
   const int nst = (In + 16 * vw - 1) / (16 * vw);
   const int rt = (R + 15) / 16;
   const int u = kChunkSteps / vw / rt;
@@ -182,7 +192,7 @@ inline int max_ksplit(int In, int dtype, int B, int R) {
 
 // Default K-split when no tuned value is given.
 inline int host_ksplit(int In, int dtype, int B, int R) {
-  const int vw = dtype == CPD_BF16 ? 2 : 1;
+  const int vw = host_vw(In, dtype);
   const int nst = (In + 16 * vw - 1) / (16 * vw);
   if (nst >= kWaves) return 1;
   int ks = kWaves / nst;
@@ -197,9 +207,10 @@ inline int host_ksplit(int In, int dtype, int B, int R) {
 // RT 16-row rank tiles (RT >= ceil(R / 16)).
 struct LdsPlan {
   size_t cdf, idx, ratio, words, wf, rinv, rowoff, wht, gs, gsp, mbuf, gram, part, red, wts,
-      misc, sbuf, total;
+      misc, sbuf, fac, total;
   int rp16, bpad, ms, imax, sumdims, nd, nblk;
   int has_sbuf;  // AdaGrad accumulators of the updated mode staged in LDS
+  int has_fac;   // every factor resident in LDS (sampled rows read from there)
 };
 
 __host__ __device__ inline LdsPlan lds_plan(int N, const int32_t* dims, int R, int B, int RT) {
@@ -245,6 +256,10 @@ __host__ __device__ inline LdsPlan lds_plan(int N, const int32_t* dims, int R, i
   const size_t sbytes = sizeof(float) * (size_t)p.imax * p.ms;
   p.has_sbuf = off + sbytes <= kLdsBudget;
   p.sbuf = p.has_sbuf ? take(sbytes) : 0;
+  // all factors, compact rows (factor k at row offset sum_{m<k} dims[m])
+  const size_t fbytes = sizeof(float) * (size_t)p.sumdims * R;
+  p.has_fac = off + fbytes <= kLdsBudget;
+  p.fac = p.has_fac ? take(fbytes) : 0;
   p.total = off;
   return p;
 }

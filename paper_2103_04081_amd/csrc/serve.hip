@@ -220,7 +220,7 @@ void admission_loop(cpd_server* s) {
         plan_workspace(&s->queue.front().req.problem, &s->queue.front().req.options, &plan, &why);
         return s->heap.alloc(plan.total, &off);
       };
-      s->cv.wait(lk, ready);
+      while (!ready()) s->cv.wait_for(lk, std::chrono::milliseconds(20));
       if (s->stop.load()) return;
       w = s->queue.front();
       s->queue.pop_front();
@@ -560,7 +560,7 @@ cpd_status cpd_submit(cpd_server* s, const cpd_request* r, uint64_t* ticket) {
     s->queue.push_back(Waiting{t, *r, now_s()});
     s->live.insert(t);
     *ticket = t;
-    s->cv.notify_one();
+    s->cv.notify_all();  // both server threads wait on this variable
     return CPD_OK;
   } catch (...) {
     set_error("unexpected exception in cpd_submit");

@@ -33,8 +33,8 @@ extern __shared__ __align__(16) unsigned char cpd_smem[];
 // space (DS instructions) instead of generic pointers.
 struct Smem {
   uint32_t o_cdf, o_idx, o_ratio, o_words, o_wf, o_rinv, o_rowoff, o_wht, o_gs, o_gsp, o_mbuf,
-      o_gram, o_part, o_red, o_wts, o_misc, o_sbuf;
-  int rp16, bpad, ms, nd, nblk, has_sbuf;
+      o_gram, o_part, o_red, o_wts, o_misc, o_sbuf, o_fac;
+  int rp16, bpad, ms, nd, nblk, has_sbuf, has_fac;
   __device__ double* cdf() const { return (double*)(cpd_smem + o_cdf); }
   __device__ int32_t* idx() const { return (int32_t*)(cpd_smem + o_idx); }        // [f][slot]
   __device__ double* ratio() const { return (double*)(cpd_smem + o_ratio); }      // [slot][f]
@@ -49,6 +49,8 @@ struct Smem {
   __device__ float* gsp() const { return (float*)(cpd_smem + o_gsp); }            // Gs partials
   __device__ float* mbuf() const { return (float*)(cpd_smem + o_mbuf); }          // rows [I_n][ms]
   __device__ float* sbuf() const { return (float*)(cpd_smem + o_sbuf); }          // S^(n) rows
+  // resident factors: A^(k)(i, r) at fac()[(coff()[k] + i) * R + r]
+  __device__ float* fac() const { return (float*)(cpd_smem + o_fac); }
   __device__ double* gram() const { return (double*)(cpd_smem + o_gram); }
   __device__ double* part() const { return (double*)(cpd_smem + o_part); }
   __device__ double* red() const { return (double*)(cpd_smem + o_red); }
@@ -341,10 +343,11 @@ __device__ __forceinline__ void prefetch_issue(const ChainDesc* dp, const Smem& 
   const CPD_GLOBAL float* An = gmem(dp->A[n]);
   const CPD_GLOBAL float* Sn = gmem(dp->S[n]);
   const bool ss = S.has_sbuf && dp->rule == CPD_RULE_ADAGRAD;
+  const float* Af = S.fac() + S.coff()[n] * dp->R;
 #pragma unroll
   for (int j = 0; j < kPrefetch; ++j) {
     const int e = threadIdx.x + j * kBlock;
-    v[j] = e < total ? An[e] : 0.f;
+    v[j] = e < total ? (S.has_fac ? Af[e] : An[e]) : 0.f;
     sv[j] = (ss && e < total) ? Sn[e] : 0.f;
   }
 }
@@ -367,10 +370,25 @@ __device__ __forceinline__ void prefetch_commit(const ChainDesc* dp, const Smem&
   }
   const CPD_GLOBAL float* An = gmem(dp->A[n]);
   const CPD_GLOBAL float* Sn = gmem(dp->S[n]);
-  for (int e = threadIdx.x + kPrefetch * kBlock; e < total; e += kBlock) {
-    const int i = e / R;
-    mbuf[i * ms + (e - i * R)] = An[e];
-    if (ss) sbuf[i * ms + (e - i * R)] = Sn[e];
+  const float* Af = S.fac() + S.coff()[n] * R;
+  // the rest in rounds whose loads are all issued before the first store
+  for (int e0 = threadIdx.x + kPrefetch * kBlock; e0 < total; e0 += kPrefetch * kBlock) {
+    float a[kPrefetch], b[kPrefetch];
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) {
+      const int e = e0 + j * kBlock;
+      a[j] = e < total ? (S.has_fac ? Af[e] : An[e]) : 0.f;
+      b[j] = (ss && e < total) ? Sn[e] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) {
+      const int e = e0 + j * kBlock;
+      if (e < total) {
+        const int i = e / R;
+        mbuf[i * ms + (e - i * R)] = a[j];
+        if (ss) sbuf[i * ms + (e - i * R)] = b[j];
+      }
+    }
   }
   const int padc = ms - R;
   for (int e = threadIdx.x; e < In * padc; e += kBlock) {
@@ -379,18 +397,45 @@ __device__ __forceinline__ void prefetch_commit(const ChainDesc* dp, const Smem&
   }
 }
 
+// A uniform value kept in a vector register: the compiler may not re-load it
+// from the descriptor (a scalar load and a full wait) every time it is used.
+template <typename T>
+__device__ __forceinline__ T in_vgpr(T x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Step-rule parameters of one step, held in vector registers.
+struct UpdateParams {
+  float alpha_t, eta, b;
+  int ada, nonneg;
+};
+
+__device__ __forceinline__ UpdateParams update_params(const ChainDesc* dp, uint64_t t) {
+  UpdateParams u;
+  u.alpha_t = in_vgpr(dp->rule == CPD_RULE_DECREASING
+                          ? (float)(dp->beta / ((double)t + dp->gamma))
+                          : dp->alpha);
+  u.eta = in_vgpr(dp->eta);
+  u.b = in_vgpr(dp->b);
+  u.ada = in_vgpr((int)(dp->rule == CPD_RULE_ADAGRAD));
+  u.nonneg = in_vgpr(dp->nonneg);
+  return u;
+}
+
 // The update of one entry: returns the new value, updates the accumulator.
-__device__ __forceinline__ float update_entry(const ChainDesc* dp, float a, float g, float& sacc,
-                                              float alpha_t) {
+__device__ __forceinline__ float update_entry(const UpdateParams& u, float a, float g,
+                                              float& sacc) {
   float an;
-  if (dp->rule == CPD_RULE_ADAGRAD) {
+  if (u.ada) {
     sacc = sacc + g * g;
-    const float den = sqrtf(dp->b + sacc);
-    an = den > 0.f ? a - dp->eta * g / den : a;
+    const float d2 = u.b + sacc;
+    // eta g / sqrt(b + S) with the hardware reciprocal square root (1 ulp)
+    an = d2 > 0.f ? a - u.eta * g * __builtin_amdgcn_rsqf(d2) : a;
   } else {
-    an = a - alpha_t * g;
+    an = a - u.alpha_t * g;
   }
-  if (dp->nonneg) an = fmaxf(an, 0.f);
+  if (u.nonneg) an = fmaxf(an, 0.f);
   return an;
 }
 
@@ -405,7 +450,7 @@ __device__ __forceinline__ float update_entry(const ChainDesc* dp, float a, floa
 // with two register buffers.
 // ---------------------------------------------------------------------------
 template <int VW, int RT, bool BF16>
-__device__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint64_t t) {
+__device__ __forceinline__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint64_t t) {
   constexpr int U = kChunkSteps / VW / RT;  // K-steps per part of the fibre range
   const int lane = threadIdx.x & 63;
   const int wave = uniform_int(threadIdx.x >> 6);
@@ -421,9 +466,7 @@ __device__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint6
   CPD_GLOBAL float* An = gmem(dp->A[n]);
   CPD_GLOBAL float* Sn = gmem(dp->S[n]);
   const bool ada = dp->rule == CPD_RULE_ADAGRAD;
-  const float alpha_t = dp->rule == CPD_RULE_DECREASING
-                            ? (float)(dp->beta / ((double)t + dp->gamma))
-                            : dp->alpha;
+  const UpdateParams up = update_params(dp, t);
   float* mbuf = S.mbuf();
 
   int nitems, c0, c1, st_first, kc = 0;
@@ -504,7 +547,7 @@ __device__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint6
             // loads in flight; the rows are written back after the phase
             const float g = -acc[rt][v][q];
             float sacc = ada ? S.sbuf()[i * ms + r] : 0.f;
-            const float an = update_entry(dp, mbuf[i * ms + r], g, sacc, alpha_t);
+            const float an = update_entry(up, mbuf[i * ms + r], g, sacc);
             if (ada) S.sbuf()[i * ms + r] = sacc;
             if (!isfinite(an)) bad = true;
             mbuf[i * ms + r] = an;
@@ -564,11 +607,17 @@ __device__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint6
           acc2[rt][v] = f4{0.f, 0.f, 0.f, 0.f};
         }
     }
+    // all A operands of the chunk first: one wait for the LDS reads, not one
+    // per group of four K-steps
+    f4 wa[U / 4][RT];
+#pragma unroll
+    for (int u4 = 0; u4 < U / 4; ++u4)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        wa[u4][rt] = *(const f4*)(wht + ((kq0 + u4) * RT + rt) * 256 + lane * 4);
 #pragma unroll
     for (int u4 = 0; u4 < U / 4; ++u4) {
-      f4 a4[RT];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) a4[rt] = *(const f4*)(wht + ((kq0 + u4) * RT + rt) * 256 + lane * 4);
+      const f4* a4 = wa[u4];
 #pragma unroll
       for (int j = 0; j < 4; j += 2)
 #pragma unroll
@@ -633,25 +682,83 @@ __device__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint6
   if (direct) {
     // write the updated rows (and accumulators) back, coalesced
     __syncthreads();
+    float* Af = S.fac() + S.coff()[n] * R;
     for (int e = threadIdx.x; e < In * R; e += kBlock) {
       const int i = e / R, r = e - i * R;
-      An[e] = mbuf[i * ms + r];
+      const float a = mbuf[i * ms + r];
+      An[e] = a;
+      if (S.has_fac) Af[e] = a;
       if (ada) Sn[e] = S.sbuf()[i * ms + r];
     }
   } else {
     // element-wise update from -G^T in mbuf
+    float* Af = S.fac() + S.coff()[n] * R;
     for (int e = threadIdx.x; e < In * R; e += kBlock) {
       const int i = e / R, r = e - i * R;
       const float g = -mbuf[i * ms + r];
       float sacc = ada ? Sn[e] : 0.f;
-      const float an = update_entry(dp, An[e], g, sacc, alpha_t);
+      const float an = update_entry(up, S.has_fac ? Af[e] : An[e], g, sacc);
       if (ada) Sn[e] = sacc;
       if (!isfinite(an)) bad = true;
       An[e] = an;
+      if (S.has_fac) Af[e] = an;
       mbuf[i * ms + r] = an;
     }
   }
   return bad;
+}
+
+// The BF16 contraction as a call of its own: it then gets the whole
+// register file instead of sharing it with the rest of the step, which
+// schedules it better (measured).
+template <int RT>
+__device__ __noinline__ bool contract_update_bf16(const ChainDesc* dp, const Smem& S, int n,
+                                                  uint64_t t) {
+  return contract_update<2, RT, true>(dp, S, n, t);
+}
+
+// WH rows of the sampled fibres, CPI columns per item (one rank tile holds
+// 16 / CPI items).  Factor rows come from the resident LDS copy when there
+// is one.
+template <int CPI, int RT>
+__device__ __forceinline__ void krp_rows(const ChainDesc* dp, const Smem& S, int n, int B, int nm1,
+                                         float* wht) {
+  const int R = dp->R;
+  constexpr int ipf = 16 * RT / CPI;
+  for (int itm = threadIdx.x; itm < S.bpad * ipf; itm += kBlock) {
+    const int f = itm / ipf, c0 = (itm - f * ipf) * CPI;
+    float h[CPI];
+#pragma unroll
+    for (int c = 0; c < CPI; ++c) h[c] = 0.f;
+    float wfl = 0.f;
+    if (f < B) {
+      double p = 1.0;
+      for (int sl = 0; sl < nm1; ++sl) p = p * S.ratio()[sl * B + f];
+      wfl = (float)(1.0 / ((double)B * p));
+      for (int q = 0; q < nm1; ++q) {
+        const int k = q < n ? q : q + 1;
+        const int i = S.idx()[f * nm1 + q];
+        float v[CPI];
+        if (S.has_fac) {
+          const float* row = S.fac() + (S.coff()[k] + i) * R;
+#pragma unroll
+          for (int c = 0; c < CPI; ++c) v[c] = c0 + c < R ? row[c0 + c] : 0.f;
+        } else {
+          const CPD_GLOBAL float* row = gmem(dp->A[k]) + (int64_t)i * R;
+#pragma unroll
+          for (int c = 0; c < CPI; ++c) v[c] = c0 + c < R ? row[c0 + c] : 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < CPI; ++c) h[c] = q == 0 ? v[c] : h[c] * v[c];
+      }
+    }
+    const int k4 = f >> 2, g4 = f & 3;
+#pragma unroll
+    for (int c = 0; c < CPI; ++c) {
+      const int col = c0 + c;
+      wht[wht_index(k4, col >> 4, g4 * 16 + (col & 15), RT)] = wfl * h[c];
+    }
+  }
 }
 
 // first i in [0, Ik) with C[i] > tg (C ascending, C[Ik-1] > tg)
@@ -695,6 +802,8 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
   S.o_misc = P.misc;
   S.o_sbuf = P.sbuf;
   S.has_sbuf = P.has_sbuf;
+  S.o_fac = P.fac;
+  S.has_fac = P.has_fac;
   S.rp16 = P.rp16;
   S.bpad = P.bpad;
   S.ms = P.ms;
@@ -711,6 +820,12 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
   __syncthreads();
   for (int k = 0; k < N; ++k)
     for (int i = tid; i < dp->dims[k]; i += kBlock) S.cdf()[S.coff()[k] + i] = gmem(dp->C[k])[i];
+  if (S.has_fac && args.op != OP_REFRESH)
+    for (int k = 0; k < N; ++k) {
+      const CPD_GLOBAL float* Ak = gmem(dp->A[k]);
+      float* dst = S.fac() + S.coff()[k] * R;
+      for (int e = tid; e < dp->dims[k] * R; e += kBlock) dst[e] = Ak[e];
+    }
 
   if (args.op == OP_REFRESH) {
     __syncthreads();
@@ -800,12 +915,12 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
       break;
     }
     if (tid == 0) S.misc()[4] = 0;
-    // ---- 2. one thread per fibre: p_f, w_f, row offset, WH row ----------
+    // ---- 2. per fibre: p_f, w_f, row offset; WH rows 4 columns per item ----
     const int ldn = dp->ld[n];
     const int64_t esz = dp->dtype == CPD_BF16 ? 2 : 4;
     float* wht = S.wht();
     for (int f = tid; f < S.bpad; f += kBlock) {
-      const int k4 = f >> 2, g4 = f & 3;
+      const int ro = (f >> 4) * 16 + (f & 3) * 4 + ((f >> 2) & 3);
       if (f < B) {
         double p = 1.0;
         int64_t j = 0, stride = 1;
@@ -817,53 +932,27 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
           stride *= dp->dims[k];
           ++sl;
         }
-        const float wfl = (float)(1.0 / ((double)B * p));
-        S.wf()[f] = wfl;
+        S.wf()[f] = (float)(1.0 / ((double)B * p));
         S.rinv()[f] = (float)((double)B * p);
-        S.rowb()[(f >> 4) * 16 + (f & 3) * 4 + ((f >> 2) & 3)] = (uint32_t)(j * ldn * esz);
+        S.rowb()[ro] = (uint32_t)(j * ldn * esz);
         if (args.op == OP_SAMPLE) {
           gmem(args.out_p)[f] = p;
           for (int q = 0; q < nm1; ++q) gmem(args.out_idx)[f * nm1 + q] = S.idx()[f * nm1 + q];
         }
-        // sampled KRP row: product over k != n (ascending) of A^(k)(i_k, :),
-        // 16 columns at a time, the loads of up to three rows issued together
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          const int r0 = rt * 16;
-          float h[16];
-          for (int q0 = 0; q0 < nm1; q0 += 3) {
-            float v[3][16];
-#pragma unroll
-            for (int qq = 0; qq < 3; ++qq) {
-              const int q = q0 + qq;
-              if (q < nm1) {
-                const int k = q < n ? q : q + 1;
-                const CPD_GLOBAL float* row = gmem(dp->A[k]) + (int64_t)S.idx()[f * nm1 + q] * R;
-#pragma unroll
-                for (int c = 0; c < 16; ++c) v[qq][c] = r0 + c < R ? row[r0 + c] : 0.f;
-              } else {
-#pragma unroll
-                for (int c = 0; c < 16; ++c) v[qq][c] = 1.f;
-              }
-            }
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-              const float prod = (v[0][c] * v[1][c]) * v[2][c];
-              h[c] = q0 == 0 ? prod : h[c] * prod;
-            }
-          }
-#pragma unroll
-          for (int c = 0; c < 16; ++c) wht[wht_index(k4, rt, g4 * 16 + c, RT)] = wfl * h[c];
-        }
       } else {
         S.wf()[f] = 0.f;
         S.rinv()[f] = 0.f;
-        S.rowb()[(f >> 4) * 16 + (f & 3) * 4 + ((f >> 2) & 3)] = 0;
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-          for (int c = 0; c < 16; ++c) wht[wht_index(k4, rt, g4 * 16 + c, RT)] = 0.f;
+        S.rowb()[ro] = 0;
       }
+    }
+    // sampled KRP row H(f, c) = prod over k != n (ascending) of A^(k)(i_k, c),
+    // scaled by w_f (recomputed here exactly as above); items of 4, 8 or 16
+    // columns so that about one item per thread covers the batch
+    {
+      const int work = S.bpad * RT;
+      if (work >= kBlock) krp_rows<16, RT>(dp, S, n, B, nm1, wht);
+      else if (work >= kBlock / 2) krp_rows<8, RT>(dp, S, n, B, nm1, wht);
+      else krp_rows<4, RT>(dp, S, n, B, nm1, wht);
     }
     if (args.op == OP_SAMPLE) {
       if (tid == 0) *gmem(args.out_mode) = n;
@@ -886,7 +975,7 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
     compute_gs<RT>(S);
     // ---- 4. contraction and update -----------------------------------------
     bool bad;
-    if (dp->dtype == CPD_BF16) bad = contract_update<2, RT, true>(dp, S, n, t);
+    if (dp->dtype == CPD_BF16) bad = contract_update_bf16<RT>(dp, S, n, t);
     else bad = contract_update<1, RT, false>(dp, S, n, t);
     if (bad) S.misc()[1] = CPD_E_DIVERGED;
     __syncthreads();
