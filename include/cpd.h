@@ -194,6 +194,26 @@ CPD_API cpd_status cpd_read_cdf(cpd_handle* h, int32_t n, double* dst);
 CPD_API cpd_status cpd_read_state(cpd_handle* h, void* buf, size_t* bytes);
 CPD_API cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes);
 
+/*
+ * cpd_variance: the exact variance of the sampled gradient of mode n at the
+ * current factors, for mini-batches of the handle's B drawn by `sampler`
+ * (any of the three, independent of the handle's own), from the variance
+ * theorem of Section 4 (Table 1 lists its per-sampler forms):
+ *   out[0] = E ||G - grad f||_F^2
+ *          = (1/B) (sum_j ||r_j||^2 ||z_j||^2 / p_j - ||grad f||_F^2),
+ *   out[1] = (1/B) sum_j ||r_j||^2 ||z_j||^2 / p_j,
+ *   out[2] = (1/B) ||grad f||_F^2,
+ * with z_j row j of the Khatri-Rao product Z^(n), r_j = A^(n) z_j - x_j the
+ * residual of fibre j, p_j = prod_{k != n} q_k(i_k) / Q_k the probability of
+ * the integer-valued distributions the sampler builds from the current
+ * factors, and grad f = A^(n) (hadamard_{k != n} A^(k)T A^(k)) - X_(n) Z^(n).
+ * Two passes over copy n; FP32 products, FP64 sums.  Synchronous; uses
+ * temporary device memory (about 128 KiB * R for the partial sums, plus the
+ * distributions).  The handle's state is not changed.
+ * Errors: CPD_E_INVALID, CPD_E_RANK_DEFICIENT (leverage), CPD_E_HIP.
+ */
+CPD_API cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, double* out);
+
 /* Release the handle (the workspace stays the caller's). */
 CPD_API cpd_status cpd_destroy(cpd_handle* h);
 

@@ -10,5 +10,5 @@ from .cpdmi import (  # noqa: F401
     cpd_server_stats, cpd_submit, cpd_batch_create, cpd_batch_destroy, cpd_batch_fits,
     cpd_batch_member_info, cpd_batch_read_factors, cpd_batch_run, cpd_batch_step, cpd_batch_sync,
     cpd_batch_workspace_size, cpd_destroy, cpd_fit, cpd_get_step, cpd_init, cpd_read_cdf,
-    cpd_read_factors, cpd_read_state, cpd_sample, cpd_step, cpd_step_replay, cpd_sync,
+    cpd_read_factors, cpd_read_state, cpd_sample, cpd_step, cpd_step_replay, cpd_sync, cpd_variance,
     cpd_workspace_size, cpd_write_state, lib, make_options, make_problem)

@@ -109,6 +109,7 @@ def lib():
             "cpd_read_state": (st, [H, ctypes.c_void_p, P(ctypes.c_size_t)]),
             "cpd_write_state": (st, [H, ctypes.c_void_p, ctypes.c_size_t]),
             "cpd_destroy": (st, [H]),
+            "cpd_variance": (st, [H, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -257,6 +258,14 @@ def cpd_read_state(h):
 def cpd_write_state(h, blob):
     buf = ctypes.create_string_buffer(blob, len(blob))
     return check(lib().cpd_write_state(h, buf, len(blob)), "cpd_write_state")
+
+
+def cpd_variance(h, n, sampler):
+    """(variance, (1/B) sum of the terms, (1/B) ||grad f||^2) for mode n."""
+    out = (ctypes.c_double * 3)()
+    s = SAMPLER[sampler] if isinstance(sampler, str) else int(sampler)
+    check(lib().cpd_variance(h, int(n), s, out), "cpd_variance")
+    return out[0], out[1], out[2]
 
 
 def cpd_destroy(h):
@@ -530,6 +539,10 @@ class Decomposition:
         idx_t = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32), device=self.device)
         cpd_step_replay(self.h, mode, idx_t.data_ptr())
         self.sync()
+
+    def variance(self, n, sampler):
+        """Exact variance of the sampled gradient of mode n under ``sampler``."""
+        return cpd_variance(self.h, n, sampler)
 
     def state(self):
         return cpd_read_state(self.h)

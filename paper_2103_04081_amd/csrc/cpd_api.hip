@@ -620,6 +620,18 @@ cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes) {
   return device_status(h);
 }
 
+cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, double* out) {
+  if (!h || !out || n < 0 || n >= h->p.N || sampler < 0 || sampler > 2) {
+    set_error("bad argument");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  s = device_status(h);
+  if (s != CPD_OK) return s;
+  return variance_eval(h->desc, h->plan.lds, n, sampler, h->stream, out);
+}
+
 cpd_status cpd_destroy(cpd_handle* h) {
   if (!h) return CPD_OK;
   (void)hipSetDevice(h->device);

@@ -53,6 +53,10 @@ cpd_status check_input_kinds(int x_dtype, int x_space);
 // Message for a sticky device status (sets the thread's last error).
 void describe_status(cpd_status s);
 
+// Exact variance of the sampled gradient of mode n (variance.hip).
+cpd_status variance_eval(const ChainDesc& host_desc, size_t lds, int n, int sampler,
+                         hipStream_t stream, double* out3);
+
 void set_error(const std::string& msg);
 cpd_status hip_fail(hipError_t e, const char* what);
 

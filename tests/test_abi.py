@@ -29,7 +29,7 @@ def test_headers_declare_entry_points():
                  "cpd_batch_workspace_size", "cpd_batch_create", "cpd_batch_step",
                  "cpd_batch_fits", "cpd_batch_run", "cpd_batch_member_info",
                  "cpd_batch_destroy", "cpd_server_create", "cpd_submit", "cpd_poll",
-                 "cpd_server_stats", "cpd_server_destroy"):
+                 "cpd_server_stats", "cpd_server_destroy", "cpd_variance"):
         assert must in names, must
 
 
