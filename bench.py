@@ -83,6 +83,7 @@ def parse():
                     help="skip the per-tensor FP32 comparison of the batched section")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-variance", action="store_true", help="skip the variance study")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving section (profiling)")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -174,6 +175,8 @@ def main():
         extra["time_to_fit"] = time_to_fit(make, target=0.99, every=25, max_steps=40000)
     if not args.no_batch:
         extra["batch"] = batch_bench(args.batch_count, seq=not args.no_seq)
+    if not args.no_variance:
+        extra["variance"] = variance_study()
     if not args.no_serve:
         extra["serve"] = serve_bench(args.serve_requests)
         extra["serve_saturated"] = serve_bench(args.serve_requests, saturate=True)
@@ -367,6 +370,41 @@ def serve_bench(n_requests=200, rate=50.0, saturate=False):
         "steps_p50": pct(np.array([d["steps"] for d in done]), 50),
         "device_generation_seconds": gen_s,
     }
+
+
+def variance_study(steps=1000, every=100, B=18):
+    """The variance of the sampled gradient (mode 1, variance theorem) for the
+    three samplers along an EAdawsCPD run on the paper's Data II and Data III,
+    and the time of one evaluation (two passes over copy 1)."""
+    import numpy as np
+    import torch
+
+    import cpd_inputs as ci
+    import paper_2103_04081_amd as P
+    out = {"setting": f"300^3 from 300x10 Gaussian factors (Data II; Data III = one entry per "
+                      f"factor set to 20), no noise, B={B}, Euclidean sampler + AdaGrad eta=1 "
+                      f"driving the run; mode 1 variances at every {every} steps"}
+    for which in (2, 3):
+        w = ci.variance_data(which)
+        dec = P.Decomposition(np.asfortranarray(w["X"].astype(np.float32)), w["A0"], B=B,
+                              sampler="euclidean", eta=1.0, seed=3010 + which)
+        rows = []
+        for t in range(0, steps + 1, every):
+            if t:
+                dec.step(every)
+            v = {s: dec.variance(0, s)[0] for s in ("uniform", "leverage", "euclidean")}
+            rows.append({"t": t, **v})
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dec.variance(0, "euclidean")
+        el = (time.perf_counter() - t0) / 5
+        nbytes = 2 * 300 * 320 * 300 * 4  # two passes over copy 1 (rows padded to 320)
+        out[f"data_{'ii' if which == 2 else 'iii'}"] = rows
+        out[f"data_{'ii' if which == 2 else 'iii'}_eval_seconds"] = el
+        out[f"data_{'ii' if which == 2 else 'iii'}_eval_gbps"] = nbytes / el / 1e9
+        dec.close()
+    return out
 
 
 def time_to_fit(make, target, every, max_steps):

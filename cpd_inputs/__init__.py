@@ -37,6 +37,7 @@ __all__ = [
     "request_trace",
     "round_bf16",
     "device_problem",
+    "variance_data",
 ]
 
 
@@ -258,3 +259,21 @@ def device_problem(spec, device="cuda"):
         X.add_(Nz, alpha=float(sigma))
         del Nz
     return X.reshape(dims[::-1]).contiguous(), A0
+
+
+def variance_data(which, *, seed=1010, I=300, R=10):
+    """The tensors of the paper's variance comparison (Section 5): Data II is
+    built from three I x R factors with iid N(0,1) entries; Data III is Data
+    II with one uniformly chosen entry of each factor set to 20.  No noise.
+    Returns a problem dict like :func:`make_problem` (FP32 storage)."""
+    rng = rng_for(seed)
+    A = gaussian_factors([I, I, I], R, rng)
+    if which == 3:
+        for a in A:
+            a[int(rng.integers(0, a.shape[0])), int(rng.integers(0, a.shape[1]))] = 20.0
+    elif which != 2:
+        raise ValueError("which must be 2 or 3")
+    X64 = cp_full(A)
+    X = np.asfortranarray(X64.astype(np.float32).astype(np.float64))
+    A0 = init_factors([I, I, I], R, seed + 1)
+    return {"dims": [I, I, I], "R": R, "X": X, "X64": X64, "A_true": A, "A0": A0}
