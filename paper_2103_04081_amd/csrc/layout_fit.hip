@@ -230,9 +230,11 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
     }
     __syncthreads();
   }
+  const bool small_rows = J0 < ((int64_t)1 << 31);
   const int nit = (I0 + 63) / 64;
   const CPD_GLOBAL char* X0 = gmem((const char*)dp->X[0]);
   double accd = 0.0;
+  w4 va[U], vb[U];  // inner pass: chunk buffers, the first one carried across tiles
   for (int64_t t0 = r0 + 16 * wave; t0 < r1; t0 += 16 * (kFitBlock / 64)) {
     const int64_t jr = t0 + rq < J0 ? t0 + rq : J0 - 1;  // rows past the end: any valid row
     const CPD_GLOBAL w4* xr = (const CPD_GLOBAL w4*)(X0 + jr * (int64_t)ld0 * sizeof(T));
@@ -287,9 +289,15 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
         }
       }
     };
-    w4 va[U], vb[U];
+    if (t0 == r0 + 16 * wave) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) va[u] = xr[4 * u + kg];
+      for (int u = 0; u < U; ++u) va[u] = xr[4 * u + kg];
+    }
+    // the first chunk of this wave's next tile is loaded during the last
+    // chunk and the epilogue of this one
+    const int64_t tn = t0 + 16 * (kFitBlock / 64);
+    const CPD_GLOBAL w4* xn = (const CPD_GLOBAL w4*)(X0 + (tn + rq < J0 ? tn + rq : J0 - 1) *
+                                                          (int64_t)ld0 * sizeof(T));
     for (int it = 0; it < nit; it += 2) {
       if (it + 1 < nit) {
 #pragma unroll
@@ -299,6 +307,9 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
       if (it + 2 < nit) {
 #pragma unroll
         for (int u = 0; u < U; ++u) va[u] = xr[(it + 2) * Q + 4 * u + kg];
+      } else if (tn < r1) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) va[u] = xn[4 * u + kg];
       }
       if (it + 1 < nit) compute(vb, it + 1);
     }
@@ -310,11 +321,19 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
       if (j < r1) {
         float z[4] = {1.f, 1.f, 1.f, 1.f};
         int64_t rem = j;
+        uint32_t rem32 = (uint32_t)j;
         for (int k = 1; k < N; ++k) {
           const int Ik = dp->dims[k];
-          const int64_t nxt = rem / Ik;
-          const int ik = (int)(rem - nxt * Ik);
-          rem = nxt;
+          int ik;
+          if (small_rows) {
+            const uint32_t nxt = rem32 / (uint32_t)Ik;
+            ik = (int)(rem32 - nxt * (uint32_t)Ik);
+            rem32 = nxt;
+          } else {
+            const int64_t nxt = rem / Ik;
+            ik = (int)(rem - nxt * Ik);
+            rem = nxt;
+          }
           const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]) + (int64_t)ik * R;
 #pragma unroll
           for (int rt = 0; rt < 4; ++rt) {
