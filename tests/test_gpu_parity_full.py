@@ -74,3 +74,18 @@ def test_every_batch_member_f32():
                                    seed=s["seed"], stream_id=s["stream_id"],
                                    label=f"member {i}"))
     print(f"worst {worst:.3e}")
+
+
+# Shapes of the paper's hyperspectral scenes (the data themselves are not
+# available): seeded Gaussian stand-ins of the same sizes, B = 20.  The
+# 610 x 340 x 103 scene is decomposed at R = 100 in the paper; the step kernel
+# holds a factor's rows in LDS and supports R <= 64 (R = 32 at this size), so
+# the largest rank that fits is run instead.
+@pytest.mark.parametrize("dims,R,sampler", [((83, 86, 224), 10, "euclidean"),
+                                            ((145, 145, 220), 10, "leverage"),
+                                            ((610, 340, 103), 32, "euclidean")])
+def test_scene_shaped_stand_ins(dims, R, sampler):
+    prob = ci.make_problem(dims, R, data_seed=1100 + R, init_seed=1200 + R, snr_db=30.0,
+                           dtype=np.float32)
+    _replay(prob, 20, 15, sampler=sampler, storage="f32", eta=1.0, seed=1300,
+            label=f"{dims} R{R} B20 {sampler}")
