@@ -186,6 +186,13 @@ __device__ __forceinline__ void unpack16<uint16_t>(const w4& v, float* x) {
   }
 }
 
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Row stride (elements) of the BF16 copies of A^(1) the BF16 inner pass
+// stages in LDS: a multiple of 64 columns plus 8 (16-byte aligned rows whose
+// 16 rank columns start in distinct banks).
+__host__ __device__ inline int fit_a0_stride16(int I0) { return (I0 + 63) / 64 * 64 + 8; }
+
 __device__ __forceinline__ int fit_chain_of(const int32_t* start, int nchains, int bid) {
   int lo = 0, hi = nchains;
   while (hi - lo > 1) {
@@ -217,7 +224,15 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
   const int64_t r1 = r0 + rpb < J0 ? r0 + rpb : J0;
   const int RT = (R + 15) / 16;
   const int P = fit_a0_stride(I0);
-  const bool in_lds = INNER && 16 * RT * P <= lds_floats;
+  // BF16 storage: the stored values feed v_mfma_f32_16x16x32_bf16 directly,
+  // A^(1) = hi + lo as two BF16 terms (16 significant bits; products exact
+  // in FP32), staged transposed in LDS
+  constexpr bool kBf16 = sizeof(T) == 2;
+  const int P16 = fit_a0_stride16(I0);
+  const bool in_lds16 = INNER && kBf16 && 2 * 16 * RT * P16 <= 2 * lds_floats;
+  const bool in_lds = INNER && !in_lds16 && 16 * RT * P <= lds_floats;
+  uint16_t* a0h = (uint16_t*)a0t;
+  uint16_t* a0l = a0h + 16 * RT * P16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rq = lane & 15, kg = lane >> 4;
   const CPD_GLOBAL float* A0 = gmem((const float*)dp->A[0]);
@@ -227,6 +242,18 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
     for (int e = tid; e < I0 * R; e += kFitBlock) {
       const int i = e / R, col = e - i * R;
       a0t[col * P + i] = A0[e];
+    }
+    __syncthreads();
+  }
+  if (in_lds16) {
+    for (int e = tid; e < 2 * 16 * RT * P16; e += kFitBlock) a0h[e] = 0;
+    __syncthreads();
+    for (int e = tid; e < I0 * R; e += kFitBlock) {
+      const int i = e / R, col = e - i * R;
+      const float v = A0[e];
+      const uint16_t h = f32_to_bf16_rne(v);
+      a0h[col * P16 + i] = h;
+      a0l[col * P16 + i] = f32_to_bf16_rne(v - bf16_to_f32(h));
     }
     __syncthreads();
   }
@@ -260,6 +287,28 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) acc[rt] = f4{0.f, 0.f, 0.f, 0.f};
     auto compute = [&](const w4 (&v)[U], int it) {
+      if constexpr (kBf16) {
+        if (in_lds16) {
+          // K block of 32 columns per 16-byte load: lane group kg holds
+          // columns 8 kg .. 8 kg + 7 of it, the A operand as stored
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const bf8 a = __builtin_bit_cast(bf8, v[u]);
+            const int ib = 64 * it + 32 * u + 8 * kg;
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+              if (rt < RT) {
+                const int o = (16 * rt + rq) * P16 + ib;
+                const bf8 bh = __builtin_bit_cast(bf8, *(const w4*)(a0h + o));
+                const bf8 bl = __builtin_bit_cast(bf8, *(const w4*)(a0l + o));
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc[rt], 0, 0, 0);
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[rt], 0, 0, 0);
+              }
+            }
+          }
+          return;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         float x[E];
@@ -313,32 +362,67 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
       }
       if (it + 1 < nit) compute(vb, it + 1);
     }
-    // lane holds y(row 4 kg + q, column 16 rt + rq)
+    // lane holds y(row 4 kg + q, column 16 rt + rq).  z_j = A^(2)(i_2) (x)
+    // w with w the product over the higher modes, shared by the four rows
+    // unless i_2 wraps inside them (then the row takes the general path).
     float part = 0.f;
+    const int64_t jb = t0 + 4 * kg;
+    const int I1 = dp->dims[1];
+    int i1b;
+    int64_t hi;
+    if (small_rows) {
+      const uint32_t h = (uint32_t)jb / (uint32_t)I1;
+      i1b = (int)((uint32_t)jb - h * (uint32_t)I1);
+      hi = h;
+    } else {
+      hi = jb / I1;
+      i1b = (int)(jb - hi * I1);
+    }
+    float w[4] = {1.f, 1.f, 1.f, 1.f};
+    {
+      int64_t rem = hi;
+      for (int k = 2; k < N; ++k) {
+        const int Ik = dp->dims[k];
+        const int64_t nxt = small_rows ? (int64_t)((uint32_t)rem / (uint32_t)Ik) : rem / Ik;
+        const int ik = (int)(rem - nxt * Ik);
+        rem = nxt;
+        const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]) + (int64_t)ik * R;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          const int col = 16 * rt + rq;
+          if (rt < RT) w[rt] *= col < R ? Ak[col] : 0.f;
+        }
+      }
+    }
+    const CPD_GLOBAL float* A1 = gmem((const float*)dp->A[1]);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t j = t0 + 4 * kg + q;
+      const int64_t j = jb + q;
       if (j < r1) {
-        float z[4] = {1.f, 1.f, 1.f, 1.f};
-        int64_t rem = j;
-        uint32_t rem32 = (uint32_t)j;
-        for (int k = 1; k < N; ++k) {
-          const int Ik = dp->dims[k];
-          int ik;
-          if (small_rows) {
-            const uint32_t nxt = rem32 / (uint32_t)Ik;
-            ik = (int)(rem32 - nxt * (uint32_t)Ik);
-            rem32 = nxt;
-          } else {
-            const int64_t nxt = rem / Ik;
-            ik = (int)(rem - nxt * Ik);
-            rem = nxt;
-          }
-          const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]) + (int64_t)ik * R;
+        float z[4];
+        const int i1 = i1b + q;
+        if (i1 < I1) {
 #pragma unroll
           for (int rt = 0; rt < 4; ++rt) {
             const int col = 16 * rt + rq;
-            if (rt < RT) z[rt] *= col < R ? Ak[col] : 0.f;
+            z[rt] = (rt < RT && col < R) ? A1[(int64_t)i1 * R + col] * w[rt] : 0.f;
+          }
+        } else {
+          // i_2 wrapped: the general multi-index of row j
+          int64_t rem = j;
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) z[rt] = 1.f;
+          for (int k = 1; k < N; ++k) {
+            const int Ik = dp->dims[k];
+            const int64_t nxt = rem / Ik;
+            const int ik = (int)(rem - nxt * Ik);
+            rem = nxt;
+            const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]) + (int64_t)ik * R;
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+              const int col = 16 * rt + rq;
+              if (rt < RT) z[rt] *= col < R ? Ak[col] : 0.f;
+            }
           }
         }
 #pragma unroll
@@ -470,7 +554,10 @@ FitPlan plan_fit(const ChainDesc* descs, int nchains, int32_t* start) {
     if (nb < 1) nb = 1;
     if (nb > kFitParts) nb = kFitParts;
     acc += (int32_t)nb;
-    const size_t need = sizeof(float) * 16 * (size_t)((d.R + 15) / 16) * fit_a0_stride(d.dims[0]);
+    const size_t rt16 = 16 * (size_t)((d.R + 15) / 16);
+    const size_t need32 = sizeof(float) * rt16 * fit_a0_stride(d.dims[0]);
+    const size_t need16 = 2 * sizeof(uint16_t) * rt16 * fit_a0_stride16(d.dims[0]);
+    const size_t need = (d.dtype == CPD_BF16 && need16 <= kFitLdsMax) ? need16 : need32;
     if (need <= kFitLdsMax && need > fp.lds) fp.lds = need;
   }
   start[nchains] = acc;
