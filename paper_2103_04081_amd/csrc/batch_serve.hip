@@ -50,8 +50,8 @@ struct cpd_batch {
   std::vector<ChainDesc> descs;  // host mirror, by position
   ChainDesc* d_descs = nullptr;
   ChainState* d_states = nullptr;
-  int32_t* d_fitmap = nullptr;  // fit block table, by position
-  FitPlan fit{0, 0};
+  int32_t* d_fitmap = nullptr;  // fit block tables, by position
+  FitPlan fit{{0, 0}, {0, 0}};
   std::vector<Group> groups;
   int dtype = CPD_F32, fit_every = 25;
   double wall_hz = 1e8;
@@ -80,7 +80,7 @@ cpd_status plan_batch(const cpd_problem* ps, const cpd_options* os, int count,
   L->states = off;
   off = align_up(off + sizeof(ChainState) * count);
   L->fitmap = off;
-  off = align_up(off + sizeof(int32_t) * (count + 1));
+  off = align_up(off + sizeof(int32_t) * fit_table_len(count));
   L->base.resize(count);
   for (int i = 0; i < count; ++i) {
     std::string why;
@@ -430,10 +430,10 @@ cpd_status cpd_batch_create(const cpd_problem* ps, const cpd_options* os, int32_
       s = restart_members(b, A0);
       if (s != CPD_OK) return fail(s);
     }
-    std::vector<int32_t> fitmap(count + 1);
+    std::vector<int32_t> fitmap(fit_table_len(count));
     b->fit = plan_fit(b->descs.data(), count, fitmap.data());
     b->d_fitmap = (int32_t*)(b->ws + L.fitmap);
-    e = hipMemcpyAsync(b->d_fitmap, fitmap.data(), sizeof(int32_t) * (count + 1),
+    e = hipMemcpyAsync(b->d_fitmap, fitmap.data(), sizeof(int32_t) * fitmap.size(),
                        hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpyAsync(fit table)"));
     e = launch_fit(b->d_descs, b->d_fitmap, count, b->fit, b->dtype, false, b->stream);

@@ -74,7 +74,7 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
   w->parts = off;
   off = align_up(off + sizeof(double) * kFitParts);
   w->fitmap = off;
-  off = align_up(off + 2 * sizeof(int32_t));
+  off = align_up(off + sizeof(int32_t) * fit_table_len(1));
   for (int k = 0; k < p->N; ++k) {
     const size_t fb = sizeof(float) * (size_t)p->dims[k] * p->R;
     w->A[k] = off;
@@ -243,7 +243,7 @@ struct cpd_handle {
   ChainDesc desc;       // host mirror of the device descriptor
   ChainDesc* d_desc;    // in the workspace
   int32_t* d_mode;      // scratch int in the state block
-  int32_t* d_fitmap;    // fit block table (2 entries) in the workspace
+  int32_t* d_fitmap;    // fit block tables in the workspace
   FitPlan fit;
 };
 
@@ -371,7 +371,7 @@ cpd_status cpd_init(const cpd_problem* p, const cpd_options* o, const void* X, i
       delete h;
       return s;
     }
-    int32_t fitmap[2];
+    int32_t fitmap[6];
     h->fit = plan_fit(&h->desc, 1, fitmap);
     h->d_fitmap = (int32_t*)(h->ws + w.fitmap);
     e = hipMemcpyAsync(h->d_fitmap, fitmap, sizeof fitmap, hipMemcpyHostToDevice, h->stream);

@@ -14,16 +14,20 @@ hipError_t launch_layout_from_dense(const void* X, int in_dtype, const ChainDesc
                                     hipStream_t stream);
 hipError_t launch_layout_from_copy0(const ChainDesc& d, hipStream_t stream);
 hipError_t launch_copy0_from_staged(const void* staged, const ChainDesc& d, hipStream_t stream);
-// Fit work split over a set of decompositions: start[c] = first block of
-// decomposition c (start has nchains + 1 entries), lds = dynamic LDS of the
-// inner pass.
+// Fit work split over a set of decompositions.  Three block tables of
+// nchains + 1 prefix sums each (fit_table_len entries in all): the blocks of
+// every decomposition, then the same for the decompositions whose inner pass
+// stages little LDS ("light") and for the others ("heavy"), 0 blocks for the
+// rest.  The partial pass runs as one launch per non-empty group, so a few
+// decompositions that need much LDS do not lower the occupancy of all.
 struct FitPlan {
-  int32_t total_blocks;
-  size_t lds;
+  int32_t blocks[2];  // light, heavy
+  size_t lds[2];      // dynamic LDS of the inner pass per group
 };
-FitPlan plan_fit(const ChainDesc* host_descs, int nchains, int32_t* start);
-// d_start: device copy of the start table of plan_fit.
-hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_start, int nchains,
+inline int fit_table_len(int nchains) { return 3 * (nchains + 1); }
+FitPlan plan_fit(const ChainDesc* host_descs, int nchains, int32_t* tables);
+// d_tables: device copy of the tables of plan_fit.
+hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_tables, int nchains,
                       const FitPlan& fp, int dtype, bool inner, hipStream_t stream);
 
 // Offsets of every region of one decomposition's workspace.

@@ -542,30 +542,42 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
   }
 }
 
-FitPlan plan_fit(const ChainDesc* descs, int nchains, int32_t* start) {
-  FitPlan fp{0, 0};
-  int32_t acc = 0;
+constexpr size_t kFitLightLds = 32 * 1024;  // groups the inner pass by staged LDS
+
+FitPlan plan_fit(const ChainDesc* descs, int nchains, int32_t* tables) {
+  FitPlan fp{{0, 0}, {0, 0}};
+  int32_t* all = tables;
+  int32_t* grp[2] = {tables + (nchains + 1), tables + 2 * (nchains + 1)};
+  int32_t acc = 0, accg[2] = {0, 0};
   for (int c = 0; c < nchains; ++c) {
     const ChainDesc& d = descs[c];
-    start[c] = acc;
+    all[c] = acc;
+    grp[0][c] = accg[0];
+    grp[1][c] = accg[1];
     int64_t J0 = 1;
     for (int k = 1; k < d.N; ++k) J0 *= d.dims[k];
     int64_t nb = (J0 + kFitRowsMin - 1) / kFitRowsMin;
     if (nb < 1) nb = 1;
     if (nb > kFitParts) nb = kFitParts;
-    acc += (int32_t)nb;
     const size_t rt16 = 16 * (size_t)((d.R + 15) / 16);
     const size_t need32 = sizeof(float) * rt16 * fit_a0_stride(d.dims[0]);
     const size_t need16 = 2 * sizeof(uint16_t) * rt16 * fit_a0_stride16(d.dims[0]);
-    const size_t need = (d.dtype == CPD_BF16 && need16 <= kFitLdsMax) ? need16 : need32;
-    if (need <= kFitLdsMax && need > fp.lds) fp.lds = need;
+    size_t need = (d.dtype == CPD_BF16 && need16 <= kFitLdsMax) ? need16 : need32;
+    if (need > kFitLdsMax) need = 0;  // A^(1) read from global memory
+    const int g = need <= kFitLightLds ? 0 : 1;
+    acc += (int32_t)nb;
+    accg[g] += (int32_t)nb;
+    if (need > fp.lds[g]) fp.lds[g] = need;
   }
-  start[nchains] = acc;
-  fp.total_blocks = acc;
+  all[nchains] = acc;
+  grp[0][nchains] = accg[0];
+  grp[1][nchains] = accg[1];
+  fp.blocks[0] = accg[0];
+  fp.blocks[1] = accg[1];
   return fp;
 }
 
-hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_start, int nchains,
+hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_tables, int nchains,
                       const FitPlan& fp, int dtype, bool inner, hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
@@ -577,32 +589,36 @@ hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_start, int ncha
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const dim3 grid((unsigned)fp.total_blocks);
-  const size_t lds = inner ? fp.lds : 0;
-  const int lds_floats = (int)(lds / sizeof(float));
-  if (dtype == CPD_BF16) {
-    if (inner)
-      hipLaunchKernelGGL((fit_partial_kernel<uint16_t, true>), grid, dim3(kFitBlock), lds, stream,
-                         d_descs, d_start, nchains, lds_floats);
-    else
-      hipLaunchKernelGGL((fit_partial_kernel<uint16_t, false>), grid, dim3(kFitBlock), 0, stream,
-                         d_descs, d_start, nchains, 0);
-  } else {
-    if (inner)
-      hipLaunchKernelGGL((fit_partial_kernel<float, true>), grid, dim3(kFitBlock), lds, stream,
-                         d_descs, d_start, nchains, lds_floats);
-    else
-      hipLaunchKernelGGL((fit_partial_kernel<float, false>), grid, dim3(kFitBlock), 0, stream,
-                         d_descs, d_start, nchains, 0);
+  for (int g = 0; g < 2; ++g) {
+    if (fp.blocks[g] == 0) continue;
+    const int32_t* tab = d_tables + (g + 1) * (nchains + 1);
+    const dim3 grid((unsigned)fp.blocks[g]);
+    const size_t lds = inner ? fp.lds[g] : 0;
+    const int lds_floats = (int)(lds / sizeof(float));
+    if (dtype == CPD_BF16) {
+      if (inner)
+        hipLaunchKernelGGL((fit_partial_kernel<uint16_t, true>), grid, dim3(kFitBlock), lds, stream,
+                           d_descs, tab, nchains, lds_floats);
+      else
+        hipLaunchKernelGGL((fit_partial_kernel<uint16_t, false>), grid, dim3(kFitBlock), 0, stream,
+                           d_descs, tab, nchains, 0);
+    } else {
+      if (inner)
+        hipLaunchKernelGGL((fit_partial_kernel<float, true>), grid, dim3(kFitBlock), lds, stream,
+                           d_descs, tab, nchains, lds_floats);
+      else
+        hipLaunchKernelGGL((fit_partial_kernel<float, false>), grid, dim3(kFitBlock), 0, stream,
+                           d_descs, tab, nchains, 0);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   if (inner)
     hipLaunchKernelGGL((fit_final_kernel<true>), dim3(nchains), dim3(1024), 0, stream, d_descs,
-                       d_start);
+                       d_tables);
   else
     hipLaunchKernelGGL((fit_final_kernel<false>), dim3(nchains), dim3(1024), 0, stream, d_descs,
-                       d_start);
+                       d_tables);
   return hipGetLastError();
 }
 

@@ -163,7 +163,7 @@ HeaderLayout header_layout(int slots) {
     h.fit[d] = off;
     off = align_up(off + sizeof(ChainDesc) * slots);
     h.fitmap[d] = off;
-    off = align_up(off + sizeof(int32_t) * (slots + 1));
+    off = align_up(off + sizeof(int32_t) * fit_table_len(slots));
   }
   h.states = off;
   off = align_up(off + sizeof(ChainState) * slots);
@@ -183,7 +183,7 @@ cpd_status admit_one(cpd_server* s, const Waiting& w, size_t off, const WsPlan& 
   cpd_status st = init_member(p, o, w.req.X, w.req.x_dtype, w.req.x_space, w.req.A0, plan, base,
                               s->admit, desc, d_desc);
   if (st != CPD_OK) return st;
-  int32_t fitmap[2];
+  int32_t fitmap[6];
   const FitPlan fp = plan_fit(desc, 1, fitmap);
   int32_t* d_fm = (int32_t*)(base + plan.fitmap);
   hipError_t e = hipMemcpyAsync(d_fm, fitmap, sizeof fitmap, hipMemcpyHostToDevice, s->admit);
@@ -290,9 +290,9 @@ hipError_t upload_views(cpd_server* s) {
     e = hipMemcpyAsync(s->d_fit[d], s->h_fit[d].data(), sizeof(ChainDesc) * n,
                        hipMemcpyHostToDevice, s->step);
     if (e != hipSuccess) break;
-    std::vector<int32_t> fm(n + 1);
+    std::vector<int32_t> fm(fit_table_len(n));
     s->fit[d] = plan_fit(s->h_fit[d].data(), n, fm.data());
-    e = hipMemcpyAsync(s->d_fitmap[d], fm.data(), sizeof(int32_t) * (n + 1),
+    e = hipMemcpyAsync(s->d_fitmap[d], fm.data(), sizeof(int32_t) * fm.size(),
                        hipMemcpyHostToDevice, s->step);
     if (e == hipSuccess) e = hipStreamSynchronize(s->step);  // fm is released below
   }
