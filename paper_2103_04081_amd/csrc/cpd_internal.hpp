@@ -15,7 +15,7 @@ constexpr int kMaxModes = CPD_MAX_MODES;
 constexpr int kMaxRank = CPD_MAX_RANK;
 constexpr int kBlock = 512;             // threads of the persistent step workgroup
 constexpr int kWaves = kBlock / 64;
-constexpr int kFitBlock = 256;
+constexpr int kFitBlock = 512;
 constexpr int kFitParts = 4096;         // partial sums of the fit / norm kernels
 constexpr size_t kAlign = 256;
 constexpr int kLdAlign = 64;            // copy rows padded to 64 elements
@@ -23,7 +23,7 @@ constexpr int kChunkSteps = 32;         // MFMA K-steps (4 fibres each) per chun
 constexpr int kFibrePad = 4 * kChunkSteps;  // sampled fibres padded (zero weight) to full chunks
 constexpr double kRankTol = 1e-12;      // Cholesky pivot^2 <= tol * diagonal => rank deficient
 constexpr size_t kLdsBudget = 160 * 1024;  // LDS per workgroup on gfx950
-constexpr int kFitRowsMin = 128;        // rows of copy 0 per fit block, at least
+constexpr int kFitRowsMin = 256;        // rows of copy 0 per fit block, at least
 constexpr size_t kFitLdsMax = 64 * 1024;  // A^(1) staged in LDS by the fit kernel up to this
 
 // Row stride (floats) of the transposed A^(1) the fit kernel stages in LDS:

@@ -333,9 +333,9 @@ __device__ __forceinline__ void compute_gs(const Smem& S) {
 
 // A^(n) into mbuf (row i at mbuf[i * ms]) for the contraction epilogue, in
 // two halves so the loads can be in flight while the draws are searched:
-// prefetch_issue loads the first 8 * kBlock entries into registers,
-// prefetch_commit stores them (and any further rows) and zeroes the rank
-// padding columns.
+// prefetch_issue loads the first kPrefetch * kBlock entries into registers,
+// prefetch_commit stores them (and any further rows).  The rank padding
+// columns of mbuf are zeroed once per launch: nothing writes them.
 constexpr int kPrefetch = 4;
 __device__ __forceinline__ void prefetch_issue(const ChainDesc* dp, const Smem& S, int n,
                                                float (&v)[kPrefetch], float (&sv)[kPrefetch]) {
@@ -389,11 +389,6 @@ __device__ __forceinline__ void prefetch_commit(const ChainDesc* dp, const Smem&
         if (ss) sbuf[i * ms + (e - i * R)] = b[j];
       }
     }
-  }
-  const int padc = ms - R;
-  for (int e = threadIdx.x; e < In * padc; e += kBlock) {
-    const int i = e / padc;
-    mbuf[i * ms + R + (e - i * padc)] = 0.f;
   }
 }
 
@@ -810,6 +805,15 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
   S.nd = P.nd;
   S.nblk = P.nblk;
   if (tid < 8) S.misc()[tid] = 0;
+  // rank padding columns of the staged factor rows: read by the matrix-core
+  // epilogue as zeros, never written by a step
+  {
+    const int padc = P.ms - R;
+    for (int e = tid; e < P.imax * padc; e += kBlock) {
+      const int i = e / padc;
+      ((float*)(cpd_smem + P.mbuf))[i * P.ms + R + (e - i * padc)] = 0.f;
+    }
+  }
   if (tid == 0) {
     int o = 0;
     for (int k = 0; k < N; ++k) {
