@@ -48,7 +48,8 @@ extern "C" {
 
 #define CPD_MAX_MODES 8
 #define CPD_MAX_RANK 64
-#define CPD_MAX_BATCH 4096
+#define CPD_MAX_BATCH 1048576
+#define CPD_MAX_PERSISTENT_BATCH 4096  /* largest B of the one-workgroup step */
 #define CPD_MAX_DIM 4096
 
 typedef int32_t cpd_status;
@@ -75,6 +76,17 @@ enum { CPD_SAMPLER_UNIFORM = 0, CPD_SAMPLER_LEVERAGE = 1, CPD_SAMPLER_EUCLIDEAN 
 enum { CPD_RULE_FIXED = 0, CPD_RULE_ADAGRAD = 1, CPD_RULE_DECREASING = 2 };
 
 enum { CPD_F32 = 0, CPD_BF16 = 1, CPD_F64 = 2 };
+
+/* Execution of one step.  PERSISTENT: one workgroup runs many steps in one
+ * launch, every phase in its LDS (B <= CPD_MAX_PERSISTENT_BATCH and the
+ * step's LDS within 160 KiB).  GRID: every step is three launches over the
+ * whole GPU (the fibre gather and contraction split over blocks of up to
+ * 512 fibres, a fixed-order sum of the block parts with the update, the
+ * CDF refresh), for mini-batches too large for one workgroup.  AUTO picks
+ * PERSISTENT when it fits.  Both draw the same indices from the same
+ * Philox stream and CDFs; their iterates differ only in FP32 summation
+ * order.  Batched and served decompositions use PERSISTENT. */
+enum { CPD_PATH_AUTO = 0, CPD_PATH_PERSISTENT = 1, CPD_PATH_GRID = 2 };
 enum { CPD_HOST = 0, CPD_DEVICE = 1 };
 
 typedef struct cpd_problem {
@@ -103,6 +115,7 @@ typedef struct cpd_options {
                                       waves (0 = library default; see
                                       cpd_batch_member_info).  Results depend on it
                                       only through the FP32 summation order. */
+  int32_t path;                    /* how a step is executed: CPD_PATH_* */
 } cpd_options;
 
 typedef struct cpd_handle cpd_handle;
@@ -153,7 +166,7 @@ CPD_API cpd_status cpd_sample(cpd_handle* h, uint64_t t, int32_t* mode, int32_t*
 
 /*
  * cpd_step: enqueue nsteps steps (t .. t+nsteps-1) on the handle's stream
- * (one persistent launch).  Asynchronous: a non-finite factor or a sampling
+ * (one persistent launch, or three launches per step on the GRID path).  Asynchronous: a non-finite factor or a sampling
  * failure is recorded on the device and reported by the next synchronising
  * call (cpd_sync, cpd_fit, cpd_read_*).
  */

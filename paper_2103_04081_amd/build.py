@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcpdmi.so")
 
-SOURCES = ["cpd_api.hip", "step_kernel.hip", "layout_fit.hip", "batch_serve.hip", "serve.hip", "variance.hip"]
+SOURCES = ["cpd_api.hip", "step_kernel.hip", "layout_fit.hip", "batch_serve.hip", "serve.hip", "variance.hip",
+           "wide_step.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -27,6 +27,10 @@ SAMPLER = {"uniform": 0, "leverage": 1, "euclidean": 2}
 RULE = {"fixed": 0, "adagrad": 1, "decreasing": 2}
 CPD_F32, CPD_BF16, CPD_F64 = 0, 1, 2
 CPD_HOST, CPD_DEVICE = 0, 1
+CPD_PATH_AUTO, CPD_PATH_PERSISTENT, CPD_PATH_GRID = 0, 1, 2
+PATH = {"auto": CPD_PATH_AUTO, "persistent": CPD_PATH_PERSISTENT, "grid": CPD_PATH_GRID}
+MAX_PERSISTENT_BATCH = 4096
+MAX_BATCH = 1 << 20
 STORAGE = {"f32": CPD_F32, "fp32": CPD_F32, "float32": CPD_F32, "bf16": CPD_BF16,
            "bfloat16": CPD_BF16}
 
@@ -49,7 +53,8 @@ class cpd_options(ctypes.Structure):
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("storage", ctypes.c_int32), ("nonneg", ctypes.c_int32),
                 ("fit_every", ctypes.c_int32), ("fit_target", ctypes.c_double),
-                ("max_steps", ctypes.c_int64), ("ksplit", ctypes.c_int32 * MAX_MODES)]
+                ("max_steps", ctypes.c_int64), ("ksplit", ctypes.c_int32 * MAX_MODES),
+                ("path", ctypes.c_int32)]
 
 
 class cpd_member_info(ctypes.Structure):
@@ -174,7 +179,7 @@ def make_problem(dims, R, B, seed=0, stream_id=0):
 
 def make_options(sampler="euclidean", rule="adagrad", alpha=0.0, eta=1.0, b=0.0, beta=0.0,
                  gamma=1.0, storage="f32", nonneg=False, fit_every=25, fit_target=0.99,
-                 max_steps=0, ksplit=None):
+                 max_steps=0, ksplit=None, path="auto"):
     o = cpd_options()
     o.sampler = SAMPLER[sampler] if isinstance(sampler, str) else int(sampler)
     o.rule = RULE[rule] if isinstance(rule, str) else int(rule)
@@ -186,6 +191,7 @@ def make_options(sampler="euclidean", rule="adagrad", alpha=0.0, eta=1.0, b=0.0,
     o.max_steps = int(max_steps)
     for k, v in enumerate(ksplit or []):
         o.ksplit[k] = int(v)
+    o.path = PATH[path] if isinstance(path, str) else int(path)
     return o
 
 
@@ -469,7 +475,7 @@ class Decomposition:
 
     def __init__(self, X, A0, *, B, R=None, sampler="euclidean", rule="adagrad", alpha=0.0,
                  eta=1.0, b=0.0, beta=0.0, gamma=1.0, storage="f32", nonneg=False, seed=0,
-                 stream_id=0, device="cuda", dims=None, ksplit=None):
+                 stream_id=0, device="cuda", dims=None, ksplit=None, path="auto"):
         self.device = torch.device(device)
         if isinstance(X, torch.Tensor):
             assert X.is_cuda and X.is_contiguous()
@@ -490,7 +496,7 @@ class Decomposition:
         self.dims, self.R, self.B = dims, R, int(B)
         self.problem = make_problem(dims, R, B, seed, stream_id)
         self.options = make_options(sampler, rule, alpha, eta, b, beta, gamma, storage, nonneg,
-                                    ksplit=ksplit)
+                                    ksplit=ksplit, path=path)
         self.ws_bytes = cpd_workspace_size(self.problem, self.options)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()

@@ -85,6 +85,11 @@ cpd_status plan_batch(const cpd_problem* ps, const cpd_options* os, int count,
   for (int i = 0; i < count; ++i) {
     std::string why;
     cpd_status s = plan_workspace(&ps[i], &os[i], &(*plans)[i], &why);
+    if (s == CPD_OK && (*plans)[i].grid) {
+      why = "batched members use the persistent step (B <= " +
+            std::to_string(CPD_MAX_PERSISTENT_BATCH) + ", LDS within 160 KiB)";
+      s = CPD_E_INVALID;
+    }
     if (s != CPD_OK) {
       set_error("member " + std::to_string(i) + ": " + why);
       return s;

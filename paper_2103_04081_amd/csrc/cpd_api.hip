@@ -44,6 +44,10 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
     *why = "storage must be CPD_F32 or CPD_BF16";
     return CPD_E_INVALID;
   }
+  if (o->path < CPD_PATH_AUTO || o->path > CPD_PATH_GRID) {
+    *why = "path must be CPD_PATH_AUTO, CPD_PATH_PERSISTENT or CPD_PATH_GRID";
+    return CPD_E_INVALID;
+  }
   int64_t total = 1;
   for (int k = 0; k < p->N; ++k) {
     if (p->dims[k] < 1 || p->dims[k] > CPD_MAX_DIM) {
@@ -56,8 +60,52 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
       return CPD_E_INVALID;
     }
   }
+  const size_t es = o->storage == CPD_BF16 ? 2 : 4;
+  for (int n = 0; n < p->N; ++n) {
+    const size_t copy_bytes =
+        es * (size_t)(total / p->dims[n]) * (size_t)round_up(p->dims[n], kLdAlign);
+    if (copy_bytes > ((size_t)1 << 32) - 256) {
+      *why = "each mode-major copy of the tensor must stay below 4 GiB";
+      return CPD_E_INVALID;
+    }
+  }
+  // the persistent step when it fits (or is asked for), else the grid step
+  const int RT = (p->R + 15) / 16;
+  const LdsPlan lp = lds_plan(p->N, p->dims, p->R, p->B, RT);
+  const bool fits = p->B <= CPD_MAX_PERSISTENT_BATCH && lp.total <= kLdsBudget;
+  w->grid = o->path == CPD_PATH_GRID || (o->path == CPD_PATH_AUTO && !fits);
+  w->lds = w->grid ? 0 : lp.total;
+  if (!w->grid && !fits) {
+    *why = p->B > CPD_MAX_PERSISTENT_BATCH
+               ? "the persistent step takes B <= " + std::to_string(CPD_MAX_PERSISTENT_BATCH)
+               : "problem needs " + std::to_string(lp.total) +
+                     " bytes of LDS per workgroup (limit 163840): reduce B, R or the mode sizes";
+    return CPD_E_INVALID;
+  }
+  w->wide_fb = w->wide_blocks = 0;
+  w->gather_lds = w->refresh_lds = 0;
+  if (w->grid) {
+    int fb = wide_fibres(p->B);
+    while (fb > kFibrePad && gather_plan(p->N, p->dims, RT, fb).total > kLdsBudget) fb -= kFibrePad;
+    w->gather_lds = gather_plan(p->N, p->dims, RT, fb).total;
+    w->refresh_lds = refresh_plan(p->N, p->dims, p->R, RT).total;
+    if (w->gather_lds > kLdsBudget || w->refresh_lds > kLdsBudget) {
+      *why = "the grid step needs " + std::to_string(std::max(w->gather_lds, w->refresh_lds)) +
+             " bytes of LDS per block (limit 163840): reduce R or the mode sizes";
+      return CPD_E_INVALID;
+    }
+    w->wide_fb = fb;
+    w->wide_blocks = (p->B + fb - 1) / fb;
+  }
   for (int k = 0; k < p->N; ++k) {
     const int ks = o->ksplit[k];
+    if (w->grid) {
+      if (ks != 0) {
+        *why = "ksplit applies to the persistent step only (must be 0 on the grid path)";
+        return CPD_E_INVALID;
+      }
+      continue;
+    }
     const int mx = max_ksplit(p->dims[k], o->storage, p->B, p->R);
     if (ks < 0 || ks > mx) {
       *why = "ksplit[" + std::to_string(k) + "] must be 0 (default) or in [1, " +
@@ -65,7 +113,6 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
       return CPD_E_INVALID;
     }
   }
-  const size_t es = o->storage == CPD_BF16 ? 2 : 4;
   size_t off = 0;
   w->state = off;
   off = align_up(off + sizeof(ChainState) + 64);
@@ -75,6 +122,15 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
   off = align_up(off + sizeof(double) * kFitParts);
   w->fitmap = off;
   off = align_up(off + sizeof(int32_t) * fit_table_len(1));
+  w->wide_info = w->wide_part = 0;
+  if (w->grid) {
+    int imax = 0;
+    for (int k = 0; k < p->N; ++k) imax = std::max(imax, p->dims[k]);
+    w->wide_info = off;
+    off = align_up(off + sizeof(WideInfo));
+    w->wide_part = off;
+    off = align_up(off + sizeof(float) * (size_t)w->wide_blocks * p->R * imax);
+  }
   for (int k = 0; k < p->N; ++k) {
     const size_t fb = sizeof(float) * (size_t)p->dims[k] * p->R;
     w->A[k] = off;
@@ -88,21 +144,9 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
     w->ld[n] = (int32_t)round_up(p->dims[n], kLdAlign);
     w->rows[n] = total / p->dims[n];
     w->X[n] = off;
-    const size_t copy_bytes = es * (size_t)w->rows[n] * w->ld[n];
-    if (copy_bytes > ((size_t)1 << 32) - 256) {
-      *why = "each mode-major copy of the tensor must stay below 4 GiB";
-      return CPD_E_INVALID;
-    }
-    off = align_up(off + copy_bytes);
+    off = align_up(off + es * (size_t)w->rows[n] * w->ld[n]);
   }
   w->total = off;
-  const LdsPlan lp = lds_plan(p->N, p->dims, p->R, p->B, (p->R + 15) / 16);
-  w->lds = lp.total;
-  if (w->lds > 160 * 1024) {
-    *why = "problem needs " + std::to_string(w->lds) +
-           " bytes of LDS per workgroup (limit 163840): reduce B, R or the mode sizes";
-    return CPD_E_INVALID;
-  }
   return CPD_OK;
 }
 
@@ -247,6 +291,34 @@ struct cpd_handle {
   FitPlan fit;
 };
 
+// The distributions of every mode from the current factors.
+static hipError_t refresh_all(cpd_handle* h) {
+  if (h->plan.grid)
+    return launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, nullptr, -1, h->stream);
+  StepArgs a{};
+  a.op = OP_REFRESH;
+  return launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
+}
+
+static WideArgs wide_args(cpd_handle* h, int op) {
+  WideArgs a{};
+  a.op = op;
+  a.fb = h->plan.wide_fb;
+  a.part = (float*)(h->ws + h->plan.wide_part);
+  a.info = (WideInfo*)(h->ws + h->plan.wide_info);
+  return a;
+}
+
+// Update and CDF refresh of the grid step whose gather was just enqueued.
+static hipError_t wide_finish(cpd_handle* h, const WideArgs& a) {
+  int imax = 0;
+  for (int k = 0; k < h->p.N; ++k) imax = std::max(imax, h->p.dims[k]);
+  hipError_t e = launch_wide_update(h->d_desc, a.part, h->plan.wide_blocks, a.info, imax * h->p.R,
+                                    h->stream);
+  if (e != hipSuccess || h->o.sampler == CPD_SAMPLER_UNIFORM) return e;
+  return launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, a.info, -2, h->stream);
+}
+
 static cpd_status read_state(cpd_handle* h, ChainState* st) {
   hipError_t e = hipMemcpyAsync(st, h->ws + h->plan.state, sizeof(ChainState), hipMemcpyDeviceToHost,
                                 h->stream);
@@ -376,9 +448,7 @@ cpd_status cpd_init(const cpd_problem* p, const cpd_options* o, const void* X, i
     h->d_fitmap = (int32_t*)(h->ws + w.fitmap);
     e = hipMemcpyAsync(h->d_fitmap, fitmap, sizeof fitmap, hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) return fail(e, "hipMemcpyAsync(fit table)");
-    StepArgs a{};
-    a.op = OP_REFRESH;
-    e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, w.lds, a, h->stream);
+    e = refresh_all(h);
     if (e != hipSuccess) return fail(e, "refresh kernel");
     e = launch_fit(h->d_desc, h->d_fitmap, 1, h->fit, o->storage, false, h->stream);
     if (e != hipSuccess) return fail(e, "norm kernels");
@@ -402,13 +472,24 @@ cpd_status cpd_sample(cpd_handle* h, uint64_t t, int32_t* mode, int32_t* idx_dev
   }
   cpd_status s = set_device(h);
   if (s != CPD_OK) return s;
-  StepArgs a{};
-  a.op = OP_SAMPLE;
-  a.sample_t = t;
-  a.out_idx = idx_dev;
-  a.out_p = p_dev;
-  a.out_mode = h->d_mode;
-  hipError_t e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
+  hipError_t e;
+  if (h->plan.grid) {
+    WideArgs a = wide_args(h, OP_SAMPLE);
+    a.sample_t = t;
+    a.out_idx = idx_dev;
+    a.out_p = p_dev;
+    a.out_mode = h->d_mode;
+    e = launch_wide_gather(h->d_desc, h->desc.RT, h->o.storage, h->plan.wide_blocks,
+                           h->plan.gather_lds, a, h->stream);
+  } else {
+    StepArgs a{};
+    a.op = OP_SAMPLE;
+    a.sample_t = t;
+    a.out_idx = idx_dev;
+    a.out_p = p_dev;
+    a.out_mode = h->d_mode;
+    e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "sample kernel");
   e = hipMemcpyAsync(mode, h->d_mode, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(mode)");
@@ -422,6 +503,16 @@ cpd_status cpd_step(cpd_handle* h, int64_t nsteps) {
   }
   cpd_status s = set_device(h);
   if (s != CPD_OK) return s;
+  if (h->plan.grid) {
+    const WideArgs a = wide_args(h, OP_STEP);
+    for (int64_t i = 0; i < nsteps; ++i) {
+      hipError_t e = launch_wide_gather(h->d_desc, h->desc.RT, h->o.storage, h->plan.wide_blocks,
+                                        h->plan.gather_lds, a, h->stream);
+      if (e == hipSuccess) e = wide_finish(h, a);
+      if (e != hipSuccess) return hip_fail(e, "grid step kernels");
+    }
+    return CPD_OK;
+  }
   const int64_t chunk = (int64_t)1 << 20;
   for (int64_t done = 0; done < nsteps; done += chunk) {
     StepArgs a{};
@@ -440,11 +531,21 @@ cpd_status cpd_step_replay(cpd_handle* h, int32_t mode, const int32_t* idx_dev) 
   }
   cpd_status s = set_device(h);
   if (s != CPD_OK) return s;
-  StepArgs a{};
-  a.op = OP_REPLAY;
-  a.replay_mode = mode;
-  a.replay_idx = idx_dev;
-  hipError_t e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
+  hipError_t e;
+  if (h->plan.grid) {
+    WideArgs a = wide_args(h, OP_REPLAY);
+    a.replay_mode = mode;
+    a.replay_idx = idx_dev;
+    e = launch_wide_gather(h->d_desc, h->desc.RT, h->o.storage, h->plan.wide_blocks,
+                           h->plan.gather_lds, a, h->stream);
+    if (e == hipSuccess) e = wide_finish(h, a);
+  } else {
+    StepArgs a{};
+    a.op = OP_REPLAY;
+    a.replay_mode = mode;
+    a.replay_idx = idx_dev;
+    e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "replay kernel");
   return CPD_OK;
 }
@@ -613,9 +714,7 @@ cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes) {
   hipError_t e = hipMemcpyAsync(h->ws + h->plan.state, &st, sizeof(int64_t) + sizeof(int32_t),
                                 hipMemcpyHostToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state t)");
-  StepArgs a{};
-  a.op = OP_REFRESH;
-  e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
+  e = refresh_all(h);
   if (e != hipSuccess) return hip_fail(e, "refresh kernel");
   return device_status(h);
 }
@@ -629,7 +728,8 @@ cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, double* out) 
   if (s != CPD_OK) return s;
   s = device_status(h);
   if (s != CPD_OK) return s;
-  return variance_eval(h->desc, h->plan.lds, n, sampler, h->stream, out);
+  return variance_eval(h->desc, h->plan.lds, h->plan.grid ? h->plan.refresh_lds : 0, n, sampler,
+                       h->stream, out);
 }
 
 cpd_status cpd_destroy(cpd_handle* h) {

@@ -179,11 +179,20 @@ inline int host_vw(int In, int dtype) {
   return dtype == CPD_BF16 ? 2 : 1;
 }
 
+// K-steps (four fibres each) per chunk of the contraction: the largest power
+// of two within kChunkSteps / (VW * RT) register slots, so a chunk always
+// divides the fibre padding kFibrePad.
+__host__ __device__ constexpr int chunk_steps(int vw, int rt) {
+  int u = kChunkSteps;
+  while (u > 4 && u * vw * rt > kChunkSteps) u >>= 1;
+  return u;
+}
+
 inline int max_ksplit(int In, int dtype, int B, int R) {
   const int vw = host_vw(In, dtype);
   const int nst = (In + 16 * vw - 1) / (16 * vw);
   const int rt = (R + 15) / 16;
-  const int u = kChunkSteps / vw / rt;
+  const int u = chunk_steps(vw, rt);
   const int chunks = (int)(((B + kFibrePad - 1) / kFibrePad) * kFibrePad / 4 / u);
   int m = kWaves / nst;
   if (m > chunks) m = chunks;
@@ -197,7 +206,7 @@ inline int host_ksplit(int In, int dtype, int B, int R) {
   if (nst >= kWaves) return 1;
   int ks = kWaves / nst;
   const int rt = (R + 15) / 16;
-  const int u = kChunkSteps / vw / rt;  // K-steps per chunk of the contraction
+  const int u = chunk_steps(vw, rt);  // K-steps per chunk of the contraction
   const int chunks = (int)(((B + kFibrePad - 1) / kFibrePad) * kFibrePad / 4 / u);
   if (ks > chunks) ks = chunks;
   return ks < 1 ? 1 : ks;
@@ -260,6 +269,104 @@ __host__ __device__ inline LdsPlan lds_plan(int N, const int32_t* dims, int R, i
   const size_t fbytes = sizeof(float) * (size_t)p.sumdims * R;
   p.has_fac = off + fbytes <= kLdsBudget;
   p.fac = p.has_fac ? take(fbytes) : 0;
+  p.total = off;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Grid-wide step (large mini-batches): every block of the gather kernel
+// takes a slice of up to kWideFibresMax sampled fibres.
+// ---------------------------------------------------------------------------
+constexpr int kWideFibresMax = 512;
+
+// Fibres per block of the gather kernel for mini-batch B: about 512 blocks
+// (two per CU) while the slices stay within [128, 512] fibres.
+inline int wide_fibres(int B) {
+  int fb = (int)round_up((B + 511) / 512, kFibrePad);
+  if (fb < kFibrePad) fb = kFibrePad;
+  if (fb > kWideFibresMax) fb = kWideFibresMax;
+  return fb;
+}
+
+// Mode and step of the step in flight, written by the gather kernel for the
+// update and refresh kernels that follow it on the stream.
+struct WideInfo {
+  int64_t t;
+  int32_t n;
+  int32_t pad;
+};
+
+struct WideArgs {
+  int32_t op;           // OP_STEP, OP_SAMPLE or OP_REPLAY
+  int32_t replay_mode;  // OP_REPLAY: the mode
+  int32_t force_mode1;  // OP_STEP timing runs: 1 + the mode every step uses; 0 = drawn
+  int32_t fb;           // fibres per block (a multiple of kFibrePad)
+  uint64_t sample_t;
+  const int32_t* replay_idx;
+  int32_t* out_idx;
+  double* out_p;
+  int32_t* out_mode;
+  float* part;          // per block: -G^T, R x I_n (row r holds the I_n entries)
+  WideInfo* info;
+};
+
+// LDS map of the gather kernel (one slice of fb fibres).
+struct GatherPlan {
+  size_t cdf, idx, ratio, words, wf, rinv, rowoff, wht, gs, gsp, misc, total;
+  int nwb;  // Philox blocks per mode slot
+};
+
+__host__ __device__ inline GatherPlan gather_plan(int N, const int32_t* dims, int RT, int fb) {
+  GatherPlan p;
+  int sumdims = 0;
+  for (int k = 0; k < N; ++k) sumdims += dims[k];
+  const int nm1 = N - 1, rp16 = 16 * RT, t2 = RT * RT;
+  p.nwb = fb / 4 + 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (size_t)round_up((int64_t)bytes, 16);
+    return o;
+  };
+  p.cdf = take(sizeof(double) * sumdims);
+  p.idx = take(sizeof(int32_t) * (size_t)fb * nm1);
+  p.ratio = take(sizeof(double) * (size_t)fb * nm1);
+  p.words = take(sizeof(uint64_t) * 4 * (size_t)p.nwb * nm1);
+  p.wf = take(sizeof(float) * fb);
+  p.rinv = take(sizeof(float) * fb);
+  p.rowoff = take(sizeof(uint32_t) * fb);
+  p.wht = take(sizeof(float) * (size_t)fb * rp16);
+  p.gs = take(sizeof(float) * (size_t)rp16 * rp16);
+  p.gsp = take(sizeof(float) * 256 * (size_t)(t2 > kWaves ? t2 : kWaves));
+  p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
+  p.total = off;
+  return p;
+}
+
+// LDS map of the refresh kernel (the CDF of one mode at a time).
+struct RefreshPlan {
+  size_t cdf, mbuf, gram, part, red, wts, misc, total;
+  int ms, imax;
+};
+
+__host__ __device__ inline RefreshPlan refresh_plan(int N, const int32_t* dims, int R, int RT) {
+  RefreshPlan p;
+  p.imax = 0;
+  for (int k = 0; k < N; ++k) p.imax = dims[k] > p.imax ? dims[k] : p.imax;
+  p.ms = 16 * RT + 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (size_t)round_up((int64_t)bytes, 16);
+    return o;
+  };
+  p.cdf = take(sizeof(double) * p.imax);
+  p.mbuf = take(sizeof(float) * (size_t)p.imax * p.ms);
+  p.gram = take(sizeof(double) * (size_t)R * R);
+  p.part = take(sizeof(double) * kBlock);
+  p.red = take(sizeof(double) * 2 * kWaves);
+  p.wts = take(sizeof(double) * (size_t)p.imax);
+  p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
   p.total = off;
   return p;
 }

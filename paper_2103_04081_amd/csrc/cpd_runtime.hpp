@@ -30,9 +30,24 @@ FitPlan plan_fit(const ChainDesc* host_descs, int nchains, int32_t* tables);
 hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_tables, int nchains,
                       const FitPlan& fp, int dtype, bool inner, hipStream_t stream);
 
+// Grid-wide step (wide_step.hip).  Gather: nblocks slices of a.fb fibres;
+// update: the parts of every entry of mode n summed and applied (launched
+// over max_rows * R entries); refresh: the CDF of mode `mode` (-1: every
+// mode, -2: the mode in info).
+hipError_t launch_wide_gather(const ChainDesc* d_desc, int rt, int dtype, int nblocks,
+                              size_t lds_bytes, const WideArgs& a, hipStream_t stream);
+hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nparts,
+                              const WideInfo* info, int max_entries, hipStream_t stream);
+hipError_t launch_wide_refresh(const ChainDesc* d_desc, int rt, size_t lds_bytes,
+                               const WideInfo* info, int mode, hipStream_t stream);
+
 // Offsets of every region of one decomposition's workspace.
 struct WsPlan {
   size_t state, desc, parts, fitmap;
+  int grid;                 // 1: the grid-wide step (CPD_PATH_GRID)
+  int wide_fb, wide_blocks; // grid path: fibres per gather block, gather blocks
+  size_t wide_info, wide_part;      // grid path: WideInfo, block parts
+  size_t gather_lds, refresh_lds;   // grid path: dynamic LDS of its kernels
   size_t A[kMaxModes], S[kMaxModes], C[kMaxModes];
   size_t X[kMaxModes];
   int32_t ld[kMaxModes];
@@ -58,8 +73,10 @@ cpd_status check_input_kinds(int x_dtype, int x_space);
 void describe_status(cpd_status s);
 
 // Exact variance of the sampled gradient of mode n (variance.hip).
-cpd_status variance_eval(const ChainDesc& host_desc, size_t lds, int n, int sampler,
-                         hipStream_t stream, double* out3);
+// grid_refresh_lds > 0: the distributions are rebuilt by the grid path's
+// refresh kernel (with that LDS) instead of the persistent kernel.
+cpd_status variance_eval(const ChainDesc& host_desc, size_t lds, size_t grid_refresh_lds, int n,
+                         int sampler, hipStream_t stream, double* out3);
 
 void set_error(const std::string& msg);
 cpd_status hip_fail(hipError_t e, const char* what);

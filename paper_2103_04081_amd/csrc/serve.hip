@@ -527,6 +527,11 @@ cpd_status cpd_submit(cpd_server* s, const cpd_request* r, uint64_t* ticket) {
     WsPlan plan;
     std::string why;
     cpd_status st = plan_workspace(&r->problem, &r->options, &plan, &why);
+    if (st == CPD_OK && plan.grid) {
+      why = "served requests use the persistent step (B <= " +
+            std::to_string(CPD_MAX_PERSISTENT_BATCH) + ", LDS within 160 KiB)";
+      st = CPD_E_INVALID;
+    }
     if (st != CPD_OK) {
       set_error(why);
       return st;

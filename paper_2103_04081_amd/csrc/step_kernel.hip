@@ -20,316 +20,9 @@
 //   5. the CDF of mode n from the new factor: squared row norms, or leverage
 //      scores from an FP64 Gram, a one-wave Cholesky and a forward solve per
 //      row; quantised to exact integers and prefix-summed.
-#include "cpd_internal.hpp"
+#include "step_common.hpp"
 
 namespace cpdmi {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-extern __shared__ __align__(16) unsigned char cpd_smem[];
-
-// Offsets of the LDS regions of one workgroup.  Pointers are always formed
-// from the LDS array itself so the compiler keeps them in the LDS address
-// space (DS instructions) instead of generic pointers.
-struct Smem {
-  uint32_t o_cdf, o_idx, o_ratio, o_words, o_wf, o_rinv, o_rowoff, o_wht, o_gs, o_gsp, o_mbuf,
-      o_gram, o_part, o_red, o_wts, o_misc, o_sbuf, o_fac;
-  int rp16, bpad, ms, nd, nblk, has_sbuf, has_fac;
-  __device__ double* cdf() const { return (double*)(cpd_smem + o_cdf); }
-  __device__ int32_t* idx() const { return (int32_t*)(cpd_smem + o_idx); }        // [f][slot]
-  __device__ double* ratio() const { return (double*)(cpd_smem + o_ratio); }      // [slot][f]
-  __device__ uint64_t* words() const { return (uint64_t*)(cpd_smem + o_words); }  // Philox
-  __device__ float* wf() const { return (float*)(cpd_smem + o_wf); }              // w_f
-  __device__ float* rinv() const { return (float*)(cpd_smem + o_rinv); }          // 1 / w_f
-  // byte offset of fibre f in copy n at rowb()[(f >> 4) * 16 + (f & 3) * 4 + ((f >> 2) & 3)]:
-  // the offsets of K-steps 4q..4q+3 for one lane group are one 16-byte read
-  __device__ uint32_t* rowb() const { return (uint32_t*)(cpd_smem + o_rowoff); }
-  __device__ float* wht() const { return (float*)(cpd_smem + o_wht); }            // WH, A layout
-  __device__ float* gs() const { return (float*)(cpd_smem + o_gs); }              // Gs [rp16]^2
-  __device__ float* gsp() const { return (float*)(cpd_smem + o_gsp); }            // Gs partials
-  __device__ float* mbuf() const { return (float*)(cpd_smem + o_mbuf); }          // rows [I_n][ms]
-  __device__ float* sbuf() const { return (float*)(cpd_smem + o_sbuf); }          // S^(n) rows
-  // resident factors: A^(k)(i, r) at fac()[(coff()[k] + i) * R + r]
-  __device__ float* fac() const { return (float*)(cpd_smem + o_fac); }
-  __device__ double* gram() const { return (double*)(cpd_smem + o_gram); }
-  __device__ double* part() const { return (double*)(cpd_smem + o_part); }
-  __device__ double* red() const { return (double*)(cpd_smem + o_red); }
-  __device__ double* wts() const { return (double*)(cpd_smem + o_wts); }
-  __device__ int32_t* misc() const { return (int32_t*)(cpd_smem + o_misc); }
-  __device__ int32_t* coff() const { return misc() + 8; }  // CDF offset of each mode
-};
-// misc(): [1] error, [2] rank flag, [4] next-step Philox blocks generated
-
-__device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Waits for this wave's LDS traffic and orders it against later LDS reads
-// of other lanes of the same wave.
-__device__ inline void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); }
-
-// Position of (K-step k, rank tile rt, lane) in the A-operand layout: the
-// four K-steps 4q..4q+3 of one lane are contiguous (one 16-byte LDS read).
-__device__ inline int wht_index(int k, int rt, int lane, int RT) {
-  return ((k >> 2) * RT + rt) * 256 + lane * 4 + (k & 3);
-}
-
-// ---------------------------------------------------------------------------
-// CDF of mode n from the factor rows in mbuf (row i at mbuf[i * ms]).
-// ---------------------------------------------------------------------------
-template <int RT>
-__device__ __forceinline__ int refresh_cdf(const ChainDesc* dp, const Smem& S, int n) {
-  const int R = dp->R, In = dp->dims[n];
-  const int ms = S.ms;
-  const float* mb = S.mbuf();
-  double* w = S.wts();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int err = 0;
-  if (dp->sampler == CPD_SAMPLER_LEVERAGE) {
-    // leverage scores l_i = ||L^{-1} a_i||^2 with L L^T = A^T A (FP64)
-    double* G = S.gram();
-    const int npairs = R * (R + 1) / 2;
-    if (npairs <= kBlock) {
-      // pairs x row chunks, partials summed in a fixed order
-      int nch = kBlock / npairs;
-      if (nch > In) nch = In;
-      const int pr = threadIdx.x % npairs, ch = threadIdx.x / npairs;
-      if (ch < nch) {
-        int r = 0, rem = pr;
-        while (rem >= R - r) {
-          rem -= R - r;
-          ++r;
-        }
-        const int c = r + rem;
-        double acc0 = 0.0, acc1 = 0.0;
-        int i = ch;
-        for (; i + nch < In; i += 2 * nch) {
-          acc0 += (double)mb[i * ms + r] * (double)mb[i * ms + c];
-          acc1 += (double)mb[(i + nch) * ms + r] * (double)mb[(i + nch) * ms + c];
-        }
-        if (i < In) acc0 += (double)mb[i * ms + r] * (double)mb[i * ms + c];
-        S.part()[ch * npairs + pr] = acc0 + acc1;
-      }
-      __syncthreads();
-      for (int p = threadIdx.x; p < npairs; p += kBlock) {
-        int r = 0, rem = p;
-        while (rem >= R - r) {
-          rem -= R - r;
-          ++r;
-        }
-        const int c = r + rem;
-        double acc = 0.0;
-        for (int q = 0; q < nch; ++q) acc += S.part()[q * npairs + p];
-        G[r * R + c] = acc;
-        G[c * R + r] = acc;
-      }
-    } else {
-      for (int p = threadIdx.x; p < npairs; p += kBlock) {
-        int r = 0, rem = p;
-        while (rem >= R - r) {
-          rem -= R - r;
-          ++r;
-        }
-        const int c = r + rem;
-        double acc = 0.0;
-        for (int i = 0; i < In; ++i) acc += (double)mb[i * ms + r] * (double)mb[i * ms + c];
-        G[r * R + c] = acc;
-        G[c * R + r] = acc;
-      }
-    }
-    __syncthreads();
-    // Cholesky by one wave (lane = row); the lower triangle of G becomes L
-    if (threadIdx.x < 64) {
-      bool ok = true;
-      for (int j = 0; j < R; ++j) {
-        double d = G[j * R + j];
-        const double diag = d;
-        for (int k = 0; k < j; ++k) d -= G[j * R + k] * G[j * R + k];
-        const bool okj = d > kRankTol * diag && isfinite(d);
-        ok = ok && okj;
-        const double ljj = okj ? sqrt(d) : 1.0;
-        const double inv = 1.0 / ljj;
-        for (int i = j + 1 + lane; i < R; i += 64) {
-          double v = G[i * R + j];
-          for (int k = 0; k < j; ++k) v -= G[i * R + k] * G[j * R + k];
-          G[i * R + j] = v * inv;
-        }
-        wave_lds_sync();
-        if (lane == 0) G[j * R + j] = ljj;
-        wave_lds_sync();
-      }
-      if (lane == 0 && !ok) S.misc()[2] = 1;
-    }
-    __syncthreads();
-    if (S.misc()[2]) err = CPD_E_RANK_DEFICIENT;
-    // l_i by forward substitution L y = a_i (y in registers)
-    for (int i = threadIdx.x; i < In; i += kBlock) {
-      double y[RT * 16];
-      double l = 0.0;
-#pragma unroll
-      for (int j = 0; j < RT * 16; ++j) {
-        if (j < R) {
-          double v = (double)mb[i * ms + j];
-#pragma unroll
-          for (int k = 0; k < j; ++k) v -= G[j * R + k] * y[k];
-          y[j] = v / G[j * R + j];
-          l += y[j] * y[j];
-        } else {
-          y[j] = 0.0;
-        }
-      }
-      w[i] = l;
-    }
-    __syncthreads();
-  }
-  // quantise: q_i = ceil(w_i 2^E), 2^E * max(w) * 2^ceil(log2 In) < 2^53,
-  // then the inclusive prefix sum (exact integers, so any order gives the
-  // same bits)
-  double* red = S.red();
-  double* C = S.cdf() + S.coff()[n];
-  CPD_GLOBAL double* Cg = gmem(dp->C[n]);
-  const int c = bit_length_u32((uint32_t)(In - 1));
-  if (In <= kBlock) {
-    const int i = threadIdx.x;
-    double wi = 0.0;
-    if (i < In) {
-      if (dp->sampler == CPD_SAMPLER_EUCLIDEAN) {
-        for (int r = 0; r < R; ++r) {
-          const double a = (double)mb[i * ms + r];
-          wi = wi + a * a;  // a*a is exact in FP64 for an FP32 a
-        }
-      } else if (dp->sampler == CPD_SAMPLER_UNIFORM) {
-        wi = 1.0;
-      } else {
-        wi = w[i];
-      }
-    }
-    const bool fin = i >= In || (isfinite(wi) && wi >= 0.0);
-    double m = fin ? wi : __builtin_inf();
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    if (lane == 0) red[wave] = m;
-    __syncthreads();
-    double wmax = red[0];
-    for (int j = 1; j < kWaves; ++j) wmax = fmax(wmax, red[j]);
-    if (!(wmax > 0.0) || !isfinite(wmax)) return err ? err : CPD_E_DEGENERATE;
-    int ex;
-    frexp(wmax, &ex);
-    double q = i < In ? ceil(ldexp(wi, 52 - ex - c)) : 0.0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const double u = __shfl_up(q, o);
-      if (lane >= o) q += u;
-    }
-    if (lane == 63) red[kWaves + wave] = q;
-    __syncthreads();
-    double off = 0.0;
-    for (int j = 0; j < wave; ++j) off += red[kWaves + j];
-    if (i < In) {
-      C[i] = q + off;
-      Cg[i] = q + off;
-    }
-    return err;
-  }
-  // general path (more rows than threads)
-  if (dp->sampler != CPD_SAMPLER_LEVERAGE) {
-    for (int i = threadIdx.x; i < In; i += kBlock) {
-      double acc = 0.0;
-      if (dp->sampler == CPD_SAMPLER_EUCLIDEAN) {
-        for (int r = 0; r < R; ++r) {
-          const double a = (double)mb[i * ms + r];
-          acc = acc + a * a;
-        }
-      } else {
-        acc = 1.0;
-      }
-      w[i] = acc;
-    }
-  }
-  double m = 0.0;
-  for (int i = threadIdx.x; i < In; i += kBlock)
-    m = fmax(m, (isfinite(w[i]) && w[i] >= 0.0) ? w[i] : __builtin_inf());
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-  __syncthreads();
-  if (lane == 0) red[wave] = m;
-  __syncthreads();
-  double wmax = red[0];
-  for (int j = 1; j < kWaves; ++j) wmax = fmax(wmax, red[j]);
-  if (!(wmax > 0.0) || !isfinite(wmax)) return err ? err : CPD_E_DEGENERATE;
-  int ex;
-  frexp(wmax, &ex);
-  double carry = 0.0;
-  for (int base = 0; base < In; base += kBlock) {
-    const int i = base + threadIdx.x;
-    double q = i < In ? ceil(ldexp(w[i], 52 - ex - c)) : 0.0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const double u = __shfl_up(q, o);
-      if (lane >= o) q += u;
-    }
-    __syncthreads();
-    if (lane == 63) red[kWaves + wave] = q;
-    __syncthreads();
-    double off = carry, tot = carry;
-    for (int j = 0; j < kWaves; ++j) {
-      if (j < wave) off += red[kWaves + j];
-      tot += red[kWaves + j];
-    }
-    if (i < In) {
-      C[i] = q + off;
-      Cg[i] = q + off;
-    }
-    carry = tot;
-  }
-  return err;
-}
-
-// ---------------------------------------------------------------------------
-// Gs = (WH)^T H, 16x16 tiles, the K-steps split over the waves; partial
-// tiles summed in a fixed order.  H = WH / w is recovered in the B operand.
-//   A operand (16 x 4): lane l holds WH[f0 + l/16][rt*16 + l%16]
-//   B operand (4 x 16): lane l holds H[f0 + l/16][ct*16 + l%16]
-//   D (16 x 16): lane l, element q holds row 4*(l/16)+q, column l%16
-// ---------------------------------------------------------------------------
-template <int RT>
-__device__ __forceinline__ void compute_gs(const Smem& S) {
-  const int lane = threadIdx.x & 63, wave = uniform_int(threadIdx.x >> 6);
-  const int fl = lane >> 4, cl = lane & 15;
-  constexpr int T2 = RT * RT;
-  constexpr int kparts = T2 >= kWaves ? 1 : kWaves / T2;
-  constexpr int items = T2 * kparts;
-  const int nq = S.bpad / 16;  // groups of four K-steps
-  const float* wht = S.wht();
-  const float* rinv = S.rinv();
-  float* gsp = S.gsp();
-  for (int it = wave; it < items; it += kWaves) {
-    const int tile = it % T2, kp = it / T2;
-    const int rt = tile / RT, ct = tile % RT;
-    const int q0 = kp * nq / kparts, q1 = (kp + 1) * nq / kparts;
-    f4 g = f4{0.f, 0.f, 0.f, 0.f};
-    for (int q = q0; q < q1; ++q) {
-      const f4 a4 = *(const f4*)(wht + (q * RT + rt) * 256 + lane * 4);
-      const f4 h4 = *(const f4*)(wht + (q * RT + ct) * 256 + lane * 4);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float b = h4[j] * rinv[(4 * q + j) * 4 + fl];
-        g = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[j], b, g, 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) gsp[it * 256 + (4 * fl + e) * 16 + cl] = g[e];
-  }
-  __syncthreads();
-  const int rp16 = S.rp16;
-  for (int e = threadIdx.x; e < rp16 * rp16; e += kBlock) {
-    const int r = e / rp16, s2 = e - r * rp16;
-    const int tile = (r >> 4) * RT + (s2 >> 4);
-    float acc = 0.f;
-    for (int kp = 0; kp < kparts; ++kp)
-      acc += gsp[(kp * T2 + tile) * 256 + (r & 15) * 16 + (s2 & 15)];
-    S.gs()[e] = acc;
-  }
-  __syncthreads();
-}
 
 // A^(n) into mbuf (row i at mbuf[i * ms]) for the contraction epilogue, in
 // two halves so the loads can be in flight while the draws are searched:
@@ -392,48 +85,6 @@ __device__ __forceinline__ void prefetch_commit(const ChainDesc* dp, const Smem&
   }
 }
 
-// A uniform value kept in a vector register: the compiler may not re-load it
-// from the descriptor (a scalar load and a full wait) every time it is used.
-template <typename T>
-__device__ __forceinline__ T in_vgpr(T x) {
-  asm volatile("" : "+v"(x));
-  return x;
-}
-
-// Step-rule parameters of one step, held in vector registers.
-struct UpdateParams {
-  float alpha_t, eta, b;
-  int ada, nonneg;
-};
-
-__device__ __forceinline__ UpdateParams update_params(const ChainDesc* dp, uint64_t t) {
-  UpdateParams u;
-  u.alpha_t = in_vgpr(dp->rule == CPD_RULE_DECREASING
-                          ? (float)(dp->beta / ((double)t + dp->gamma))
-                          : dp->alpha);
-  u.eta = in_vgpr(dp->eta);
-  u.b = in_vgpr(dp->b);
-  u.ada = in_vgpr((int)(dp->rule == CPD_RULE_ADAGRAD));
-  u.nonneg = in_vgpr(dp->nonneg);
-  return u;
-}
-
-// The update of one entry: returns the new value, updates the accumulator.
-__device__ __forceinline__ float update_entry(const UpdateParams& u, float a, float g,
-                                              float& sacc) {
-  float an;
-  if (u.ada) {
-    sacc = sacc + g * g;
-    const float d2 = u.b + sacc;
-    // eta g / sqrt(b + S) with the hardware reciprocal square root (1 ulp)
-    an = d2 > 0.f ? a - u.eta * g * __builtin_amdgcn_rsqf(d2) : a;
-  } else {
-    an = a - u.alpha_t * g;
-  }
-  if (u.nonneg) an = fmaxf(an, 0.f);
-  return an;
-}
-
 // ---------------------------------------------------------------------------
 // Contraction and update for mode n.  Per 16-column tile (columns col0 +
 // j*VW + v of the I_n x R output), K = padded fibres:
@@ -446,7 +97,7 @@ __device__ __forceinline__ float update_entry(const UpdateParams& u, float a, fl
 // ---------------------------------------------------------------------------
 template <int VW, int RT, bool BF16>
 __device__ __forceinline__ bool contract_update(const ChainDesc* dp, const Smem& S, int n, uint64_t t) {
-  constexpr int U = kChunkSteps / VW / RT;  // K-steps per part of the fibre range
+  constexpr int U = chunk_steps(VW, RT);  // K-steps per part of the fibre range
   const int lane = threadIdx.x & 63;
   const int wave = uniform_int(threadIdx.x >> 6);
   const int fl = lane >> 4, cl = lane & 15;
@@ -754,14 +405,6 @@ __device__ __forceinline__ void krp_rows(const ChainDesc* dp, const Smem& S, int
       wht[wht_index(k4, col >> 4, g4 * 16 + (col & 15), RT)] = wfl * h[c];
     }
   }
-}
-
-// first i in [0, Ik) with C[i] > tg (C ascending, C[Ik-1] > tg)
-__device__ inline int cdf_search(const double* C, int Ik, double tg) {
-  int pos = 0;
-  for (int len = 1 << (31 - __clz(Ik)); len > 0; len >>= 1)
-    if (pos + len <= Ik && C[pos + len - 1] <= tg) pos += len;
-  return pos < Ik ? pos : Ik - 1;
 }
 
 // RT: number of 16-row rank tiles the kernel is compiled for; a chain with

@@ -310,8 +310,8 @@ static VarPlan plan_variance(const ChainDesc& d, int n) {
   return v;
 }
 
-cpd_status variance_eval(const ChainDesc& hd, size_t lds, int n, int sampler, hipStream_t stream,
-                         double* out3) {
+cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_lds, int n,
+                         int sampler, hipStream_t stream, double* out3) {
   const VarPlan v = plan_variance(hd, n);
   char* scratch = nullptr;
   hipError_t e = hipMalloc((void**)&scratch, v.total);
@@ -337,9 +337,13 @@ cpd_status variance_eval(const ChainDesc& hd, size_t lds, int n, int sampler, hi
   ChainDesc* dd = (ChainDesc*)(scratch + v.desc);
   e = hipMemcpyAsync(dd, &d, sizeof d, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return done(hip_fail(e, "hipMemcpyAsync(desc)"));
-  StepArgs a{};
-  a.op = OP_REFRESH;
-  e = launch_chain_kernel(dd, 1, d.RT, lds, a, stream);
+  if (grid_refresh_lds > 0) {
+    e = launch_wide_refresh(dd, d.RT, grid_refresh_lds, nullptr, -1, stream);
+  } else {
+    StepArgs a{};
+    a.op = OP_REFRESH;
+    e = launch_chain_kernel(dd, 1, d.RT, lds, a, stream);
+  }
   if (e != hipSuccess) return done(hip_fail(e, "refresh kernel"));
   const int ntiles = (d.dims[n] + 15) / 16;
   hipLaunchKernelGGL(variance_mttkrp_kernel, dim3(ntiles * v.nchunks), dim3(64), 0, stream, dd, n,

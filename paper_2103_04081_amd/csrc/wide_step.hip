@@ -1,0 +1,493 @@
+// Grid-wide SGD step for mini-batches too large for one workgroup.  The
+// step is the same as the persistent kernel's (paper Section 3, Algorithms
+// 3-5; the same Philox words, integer CDFs, draws and step rules), spread
+// over the whole GPU in three launches:
+//   wide_gather_kernel   every block takes a slice of the B sampled fibres:
+//                        the Philox blocks of its draws, inverse-CDF search
+//                        over the CDFs in LDS, p_f, w_f and the WH rows, its
+//                        part of Gs = (WH)^T H, then its part of
+//                        -G^T = (WH)^T X_s - Gs A^(n)T on the matrix cores
+//                        (v_mfma_f32_16x16x4f32, fibres streamed from HBM
+//                        into the B operand), written to HBM;
+//   wide_update_kernel   sums the block parts of every entry of A^(n) in a
+//                        fixed order and applies the step rule;
+//   wide_refresh_kernel  the CDF of the updated mode (squared row norms or
+//                        leverage scores), the same code as the persistent
+//                        kernel's refresh.
+// G = A^(n) Gs - M is linear in the fibres, so the block parts add up to the
+// gradient of eq. (gradient); only the FP32 summation order differs from
+// the persistent kernel.
+#include "cpd_runtime.hpp"
+#include "step_common.hpp"
+
+namespace cpdmi {
+
+constexpr int kUpdWaves = 16;  // waves of an update block (64 entries each)
+
+template <int RT, bool BF16>
+__global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __restrict__ dp,
+                                                             WideArgs a) {
+  ChainState* st = dp->state;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = uniform_int(tid >> 6);
+  const int fl = lane >> 4, cl = lane & 15;
+  const int N = dp->N, R = dp->R, B = dp->B, nm1 = N - 1;
+  const int FB = a.fb;
+  const int f0 = blockIdx.x * FB;
+  const int nf = B - f0 < FB ? B - f0 : FB;
+  const GatherPlan P = gather_plan(N, dp->dims, RT, FB);
+  Smem S;
+  S.o_cdf = P.cdf;
+  S.o_idx = P.idx;
+  S.o_ratio = P.ratio;
+  S.o_words = P.words;
+  S.o_wf = P.wf;
+  S.o_rinv = P.rinv;
+  S.o_rowoff = P.rowoff;
+  S.o_wht = P.wht;
+  S.o_gs = P.gs;
+  S.o_gsp = P.gsp;
+  S.o_misc = P.misc;
+  S.o_mbuf = S.o_gram = S.o_part = S.o_red = S.o_wts = S.o_sbuf = S.o_fac = 0;
+  S.rp16 = 16 * RT;
+  S.bpad = (int)round_up(nf, kFibrePad);
+  S.ms = S.nd = S.nblk = S.has_sbuf = S.has_fac = 0;
+  int32_t* misc = S.misc();
+  const int64_t t = a.op == OP_SAMPLE ? (int64_t)a.sample_t : st->t;
+  // misc: [0] stop (sticky error before this launch), [1] error, [3] mode;
+  // one thread reads the status so that the whole block agrees on it
+  if (tid == 0) {
+    misc[0] = a.op != OP_SAMPLE && st->status != 0;
+    misc[1] = 0;
+    int o = 0;
+    for (int k = 0; k < N; ++k) {
+      S.coff()[k] = o;
+      o += dp->dims[k];
+    }
+    int n;
+    if (a.op == OP_REPLAY) {
+      n = a.replay_mode;
+    } else if (a.force_mode1) {
+      n = a.force_mode1 - 1;
+    } else {
+      uint64_t w0[4];
+      philox4x64_10((uint64_t)t, 0, 0, 0, dp->key0, dp->key1, w0);
+      n = (int)mulhi_u64(w0[0], (uint64_t)N);
+    }
+    misc[3] = n;
+  }
+  __syncthreads();
+  if (misc[0]) return;
+  const int n = uniform_int(misc[3]);
+  for (int k = 0; k < N; ++k) {
+    const CPD_GLOBAL double* Cg = gmem(dp->C[k]);
+    double* Cl = S.cdf() + S.coff()[k];
+    for (int i = tid; i < dp->dims[k]; i += kBlock) Cl[i] = Cg[i];
+  }
+  // ---- draws of this slice: draw d = 1 + slot * B + f uses word d % 4 of
+  // the Philox block (t, d / 4) -----------------------------------------------
+  uint64_t* words = S.words();
+  const int nwb = P.nwb;
+  if (a.op != OP_REPLAY) {
+    for (int e = tid; e < nm1 * nwb; e += kBlock) {
+      const int sl = e / nwb, j = e - sl * nwb;
+      const int64_t dfirst = 1 + (int64_t)sl * B + f0;
+      const int64_t c = (dfirst >> 2) + j;
+      if (c <= ((dfirst + nf - 1) >> 2)) {
+        uint64_t o[4];
+        philox4x64_10((uint64_t)t, (uint64_t)c, 0, 0, dp->key0, dp->key1, o);
+        words[4 * e + 0] = o[0];
+        words[4 * e + 1] = o[1];
+        words[4 * e + 2] = o[2];
+        words[4 * e + 3] = o[3];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nm1 * nf; e += kBlock) {
+    const int sl = e / nf, f = e - sl * nf;
+    const int k = sl < n ? sl : sl + 1;
+    const double* Ck = S.cdf() + S.coff()[k];
+    const int Ik = dp->dims[k];
+    const double Q = Ck[Ik - 1];
+    int i;
+    if (a.op == OP_REPLAY) {
+      // caller-supplied indices: reject any outside its mode's range
+      i = gmem(a.replay_idx)[(int64_t)(f0 + f) * nm1 + sl];
+      if (i < 0 || i >= Ik) {
+        misc[1] = CPD_E_INVALID;
+        i = 0;
+      }
+    } else {
+      const int64_t dfirst = 1 + (int64_t)sl * B + f0;
+      const int64_t d = dfirst + f;
+      const uint64_t wd = words[4 * (sl * nwb + (int)((d >> 2) - (dfirst >> 2))) + (int)(d & 3)];
+      i = cdf_search(Ck, Ik, (double)mulhi_u64(wd, (uint64_t)Q));
+    }
+    S.idx()[f * nm1 + sl] = i;
+    S.ratio()[sl * FB + f] = (Ck[i] - (i ? Ck[i - 1] : 0.0)) / Q;
+  }
+  __syncthreads();
+  if (misc[1]) {
+    if (tid == 0) st->status = misc[1];
+    return;
+  }
+  // ---- per fibre: p_f, w_f, the fibre's byte offset in copy n -------------
+  const int ldn = dp->ld[n];
+  const int64_t esz = BF16 ? 2 : 4;
+  for (int f = tid; f < S.bpad; f += kBlock) {
+    const int ro = (f >> 4) * 16 + (f & 3) * 4 + ((f >> 2) & 3);
+    if (f < nf) {
+      double p = 1.0;
+      int64_t j = 0, stride = 1;
+      int sl = 0;
+      for (int k = 0; k < N; ++k) {
+        if (k == n) continue;
+        p = p * S.ratio()[sl * FB + f];
+        j += (int64_t)S.idx()[f * nm1 + sl] * stride;
+        stride *= dp->dims[k];
+        ++sl;
+      }
+      S.wf()[f] = (float)(1.0 / ((double)B * p));
+      S.rinv()[f] = (float)((double)B * p);
+      S.rowb()[ro] = (uint32_t)(j * ldn * esz);
+      if (a.op == OP_SAMPLE) {
+        gmem(a.out_p)[f0 + f] = p;
+        for (int q = 0; q < nm1; ++q)
+          gmem(a.out_idx)[(int64_t)(f0 + f) * nm1 + q] = S.idx()[f * nm1 + q];
+      }
+    } else {
+      S.wf()[f] = 0.f;
+      S.rinv()[f] = 0.f;
+      S.rowb()[ro] = 0;
+    }
+  }
+  if (a.op == OP_SAMPLE) {
+    if (blockIdx.x == 0 && tid == 0) *gmem(a.out_mode) = n;
+    return;
+  }
+  // ---- WH rows: H(f, c) = product over k != n (ascending) of A^(k)(i_k, c),
+  // scaled by w_f (the same expression as above), four columns per item, in
+  // the A-operand order of the matrix-core instruction ----------------------
+  float* wht = S.wht();
+  {
+    constexpr int CPI = 4, ipf = 16 * RT / CPI;
+    for (int itm = tid; itm < S.bpad * ipf; itm += kBlock) {
+      const int f = itm / ipf, c0 = (itm - f * ipf) * CPI;
+      float h[CPI];
+#pragma unroll
+      for (int c = 0; c < CPI; ++c) h[c] = 0.f;
+      float wfl = 0.f;
+      if (f < nf) {
+        double p = 1.0;
+        for (int sl = 0; sl < nm1; ++sl) p = p * S.ratio()[sl * FB + f];
+        wfl = (float)(1.0 / ((double)B * p));
+        for (int q = 0; q < nm1; ++q) {
+          const int k = q < n ? q : q + 1;
+          const CPD_GLOBAL float* row = gmem(dp->A[k]) + (int64_t)S.idx()[f * nm1 + q] * R;
+#pragma unroll
+          for (int c = 0; c < CPI; ++c) {
+            const float v = c0 + c < R ? row[c0 + c] : 0.f;
+            h[c] = q == 0 ? v : h[c] * v;
+          }
+        }
+      }
+      const int k4 = f >> 2, g4 = f & 3;
+#pragma unroll
+      for (int c = 0; c < CPI; ++c) {
+        const int col = c0 + c;
+        wht[wht_index(k4, col >> 4, g4 * 16 + (col & 15), RT)] = wfl * h[c];
+      }
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    a.info->t = t;
+    a.info->n = n;
+  }
+  __syncthreads();
+  // ---- this slice's Gs -----------------------------------------------------
+  compute_gs<RT>(S);
+  // ---- this slice's -G^T, per 16-column tile of the I_n x R output ---------
+  //   A operand: lane l holds WH[f0 + l/16][rt*16 + l%16]           (LDS)
+  //   B operand: lane l holds X_s[f0 + l/16][col0 + (l%16)*VW + v]   (HBM)
+  // then K = rank with A = -Gs[rt*16 + l%16][s] and B = A^(n)[col][s].
+  constexpr int VW = BF16 ? 2 : 1;
+  constexpr int U = chunk_steps(VW, RT);  // K-steps per chunk
+  const int In = dp->dims[n];
+  const int SW = 16 * VW;
+  const int nst = (In + SW - 1) / SW;
+  const int nck = S.bpad / (4 * U);
+  const int nitems = wave < nst ? (nst - 1 - wave) / kWaves + 1 : 0;
+  const float* __restrict__ whtc = S.wht();
+  const uint32_t* __restrict__ rowb = S.rowb();
+  const CPD_GLOBAL char* __restrict__ Xb = gmem((const char*)dp->X[n]);
+  const CPD_GLOBAL float* An = gmem(dp->A[n]);
+  CPD_GLOBAL float* part = gmem(a.part) + (int64_t)blockIdx.x * R * In;
+  const int rp16 = S.rp16;
+
+  f4 acc[RT][VW], acc2[RT][VW];
+  float xa[U][VW], xb[U][VW];
+  auto load = [&](float (&x)[U][VW], int c) {
+    const int it = c / nck;
+    const int stl = wave + it * kWaves;
+    const int kq0 = (c - it * nck) * (U / 4);  // first group of four K-steps
+    const uint32_t colb = (uint32_t)((stl * SW + cl * VW) * (BF16 ? 2 : 4));
+#pragma unroll
+    for (int u4 = 0; u4 < U / 4; ++u4) {
+      const uint4 ob = *(const uint4*)(rowb + (kq0 + u4) * 16 + fl * 4);
+      const uint32_t o4[4] = {ob.x, ob.y, ob.z, ob.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const CPD_GLOBAL char* p = Xb + (o4[j] + colb);
+        const int u = 4 * u4 + j;
+        if constexpr (BF16) {
+          const uint32_t pk = *(const CPD_GLOBAL uint32_t*)p;
+          x[u][0] = __uint_as_float(pk << 16);
+          x[u][VW - 1] = __uint_as_float(pk & 0xFFFF0000u);
+        } else {
+          x[u][0] = *(const CPD_GLOBAL float*)p;
+        }
+      }
+    }
+  };
+  auto epilogue = [&](int stl) {
+    const int col0 = stl * SW;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < VW; ++v) acc[rt][v] += acc2[rt][v];
+    // -Gs A^(n)T: rank columns past R and rows past I_n read as zero
+#pragma unroll
+    for (int kk = 0; kk < 4 * RT; ++kk) {
+      const int s = 4 * kk + fl;
+      float bA[VW];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        const int i = col0 + cl * VW + v;
+        bA[v] = (s < R && i < In) ? An[(int64_t)i * R + s] : 0.f;
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const float g = -S.gs()[(rt * 16 + cl) * rp16 + s];
+#pragma unroll
+        for (int v = 0; v < VW; ++v)
+          acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, bA[v], acc[rt][v], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < VW; ++v)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = rt * 16 + 4 * fl + q;
+          const int i = col0 + cl * VW + v;
+          if (r < R && i < In) part[(int64_t)r * In + i] = acc[rt][v][q];
+        }
+  };
+  auto compute = [&](const float (&x)[U][VW], int c) {
+    const int it = c / nck;
+    const int ci = c - it * nck;
+    const int kq0 = ci * (U / 4);
+    if (ci == 0) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+          acc[rt][v] = f4{0.f, 0.f, 0.f, 0.f};
+          acc2[rt][v] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    f4 wa[U / 4][RT];
+#pragma unroll
+    for (int u4 = 0; u4 < U / 4; ++u4)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        wa[u4][rt] = *(const f4*)(whtc + ((kq0 + u4) * RT + rt) * 256 + lane * 4);
+#pragma unroll
+    for (int u4 = 0; u4 < U / 4; ++u4)
+#pragma unroll
+      for (int j = 0; j < 4; j += 2)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int v = 0; v < VW; ++v) {
+            acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[u4][rt][j], x[4 * u4 + j][v],
+                                                              acc[rt][v], 0, 0, 0);
+            acc2[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                wa[u4][rt][j + 1], x[4 * u4 + j + 1][v], acc2[rt][v], 0, 0, 0);
+          }
+    if (ci == nck - 1) epilogue(wave + it * kWaves);
+  };
+  const int total = nitems * nck;
+  if (total > 0) {
+    load(xa, 0);
+    for (int c = 0; c < total; c += 2) {
+      if (c + 1 < total) load(xb, c + 1);
+      compute(xa, c);
+      if (c + 2 < total) load(xa, c + 2);
+      if (c + 1 < total) compute(xb, c + 1);
+    }
+  }
+}
+
+// Entry e = r * I_n + i of -G^T: the block parts summed in a fixed order
+// (each wave a contiguous range of blocks, then the waves in order), then
+// the step rule on A^(n)(i, r).
+__global__ void __launch_bounds__(64 * kUpdWaves) wide_update_kernel(
+    const ChainDesc* __restrict__ dp, const float* __restrict__ part, int nparts,
+    const WideInfo* __restrict__ info) {
+  __shared__ float red[kUpdWaves][64];
+  __shared__ int stop;
+  ChainState* st = dp->state;
+  if (threadIdx.x == 0) stop = st->status != 0;
+  __syncthreads();
+  if (stop) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = info->n;
+  const int64_t t = info->t;
+  const int In = dp->dims[n], R = dp->R, E = In * R;
+  const int e = blockIdx.x * 64 + lane;
+  const int b0 = wave * nparts / kUpdWaves, b1 = (wave + 1) * nparts / kUpdWaves;
+  float s = 0.f;
+  if (e < E) {
+    const CPD_GLOBAL float* pp = gmem(part) + e;
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = pp[(int64_t)(b + j) * E];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s = s + v[j];
+    }
+    for (; b < b1; ++b) s = s + pp[(int64_t)b * E];
+  }
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && e < E) {
+    float m = red[0][lane];
+    for (int w = 1; w < kUpdWaves; ++w) m = m + red[w][lane];
+    const int r = e / In, i = e - r * In;
+    const int64_t ai = (int64_t)i * R + r;
+    const UpdateParams up = update_params(dp, (uint64_t)t);
+    CPD_GLOBAL float* An = gmem(dp->A[n]);
+    CPD_GLOBAL float* Sn = gmem(dp->S[n]);
+    float sacc = up.ada ? Sn[ai] : 0.f;
+    const float an = update_entry(up, An[ai], -m, sacc);
+    if (up.ada) Sn[ai] = sacc;
+    An[ai] = an;
+    if (!isfinite(an)) st->status = CPD_E_DIVERGED;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->t = t + 1;
+}
+
+// CDF of one mode (mode >= 0), of every mode (-1) or of the mode of the
+// step in flight (-2, after its update).
+template <int RT>
+__global__ void __launch_bounds__(kBlock) wide_refresh_kernel(const ChainDesc* __restrict__ dp,
+                                                              const WideInfo* __restrict__ info,
+                                                              int mode) {
+  ChainState* st = dp->state;
+  if (mode == -2 && st->status != 0) return;
+  const int tid = threadIdx.x;
+  const int N = dp->N, R = dp->R;
+  const RefreshPlan P = refresh_plan(N, dp->dims, R, RT);
+  Smem S;
+  S.o_cdf = P.cdf;
+  S.o_mbuf = P.mbuf;
+  S.o_gram = P.gram;
+  S.o_part = P.part;
+  S.o_red = P.red;
+  S.o_wts = P.wts;
+  S.o_misc = P.misc;
+  S.o_idx = S.o_ratio = S.o_words = S.o_wf = S.o_rinv = S.o_rowoff = S.o_wht = S.o_gs =
+      S.o_gsp = S.o_sbuf = S.o_fac = 0;
+  S.ms = P.ms;
+  S.rp16 = 16 * RT;
+  S.bpad = S.nd = S.nblk = S.has_sbuf = S.has_fac = 0;
+  // every mode's CDF goes to the same LDS region (offset 0)
+  if (tid < 8 + kMaxModes) S.misc()[tid] = 0;
+  float* mbuf = S.mbuf();
+  const int padc = P.ms - R;
+  for (int e = tid; e < P.imax * padc; e += kBlock) {
+    const int i = e / padc;
+    mbuf[i * P.ms + R + (e - i * padc)] = 0.f;
+  }
+  const int nb = mode >= 0 ? mode : (mode == -1 ? 0 : info->n);
+  const int ne = mode == -1 ? N : nb + 1;
+  int err = 0;
+  for (int n = nb; n < ne && !err; ++n) {
+    const CPD_GLOBAL float* An = gmem(dp->A[n]);
+    for (int e = tid; e < dp->dims[n] * R; e += kBlock) {
+      const int i = e / R;
+      mbuf[i * P.ms + (e - i * R)] = An[e];
+    }
+    __syncthreads();
+    err = refresh_cdf<RT>(dp, S, n);
+    __syncthreads();
+  }
+  if (tid == 0 && err) st->status = err;
+}
+
+template <int RT, bool BF16>
+static hipError_t gather_rt(const ChainDesc* d, int nblocks, size_t lds, const WideArgs& a,
+                            hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)wide_gather_kernel<RT, BF16>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((wide_gather_kernel<RT, BF16>), dim3(nblocks), dim3(kBlock), lds, s, d, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_gather(const ChainDesc* d_desc, int rt, int dtype, int nblocks,
+                              size_t lds_bytes, const WideArgs& a, hipStream_t stream) {
+  const bool bf = dtype == CPD_BF16;
+  switch (rt) {
+    case 1: return bf ? gather_rt<1, true>(d_desc, nblocks, lds_bytes, a, stream)
+                      : gather_rt<1, false>(d_desc, nblocks, lds_bytes, a, stream);
+    case 2: return bf ? gather_rt<2, true>(d_desc, nblocks, lds_bytes, a, stream)
+                      : gather_rt<2, false>(d_desc, nblocks, lds_bytes, a, stream);
+    case 3: return bf ? gather_rt<3, true>(d_desc, nblocks, lds_bytes, a, stream)
+                      : gather_rt<3, false>(d_desc, nblocks, lds_bytes, a, stream);
+    default: return bf ? gather_rt<4, true>(d_desc, nblocks, lds_bytes, a, stream)
+                       : gather_rt<4, false>(d_desc, nblocks, lds_bytes, a, stream);
+  }
+}
+
+hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nparts,
+                              const WideInfo* info, int max_entries, hipStream_t stream) {
+  const int nblocks = (max_entries + 63) / 64;
+  hipLaunchKernelGGL(wide_update_kernel, dim3(nblocks), dim3(64 * kUpdWaves), 0, stream, d_desc,
+                     part, nparts, info);
+  return hipGetLastError();
+}
+
+template <int RT>
+static hipError_t refresh_rt(const ChainDesc* d, size_t lds, const WideInfo* info, int mode,
+                             hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)wide_refresh_kernel<RT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(wide_refresh_kernel<RT>, dim3(1), dim3(kBlock), lds, s, d, info, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_refresh(const ChainDesc* d_desc, int rt, size_t lds_bytes,
+                               const WideInfo* info, int mode, hipStream_t stream) {
+  switch (rt) {
+    case 1: return refresh_rt<1>(d_desc, lds_bytes, info, mode, stream);
+    case 2: return refresh_rt<2>(d_desc, lds_bytes, info, mode, stream);
+    case 3: return refresh_rt<3>(d_desc, lds_bytes, info, mode, stream);
+    default: return refresh_rt<4>(d_desc, lds_bytes, info, mode, stream);
+  }
+}
+
+}  // namespace cpdmi

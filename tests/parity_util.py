@@ -17,7 +17,7 @@ def problem(dims, R, *, data_seed=11, init_seed=12, snr_db=30.0, storage="f32", 
 
 def gpu_decomposition(prob, B, *, sampler="euclidean", rule="adagrad", eta=0.5, alpha=0.0, b=0.0,
                       beta=0.0, gamma=1.0, storage="f32", seed=5, stream_id=0, nonneg=False,
-                      device_input=False):
+                      device_input=False, path="auto"):
     """The HIP library on the same tensor (FP32 values, rounded to BF16 by the
     library when storage is BF16) and initial factors."""
     import torch
@@ -32,7 +32,7 @@ def gpu_decomposition(prob, B, *, sampler="euclidean", rule="adagrad", eta=0.5, 
         X = X32
     return P.Decomposition(X, prob["A0"], B=B, sampler=sampler, rule=rule, eta=eta, alpha=alpha,
                            b=b, beta=beta, gamma=gamma, storage=storage, seed=seed,
-                           stream_id=stream_id, nonneg=nonneg, dims=prob["dims"])
+                           stream_id=stream_id, nonneg=nonneg, dims=prob["dims"], path=path)
 
 
 def oracle_for(prob, B, *, sampler="euclidean", rule="adagrad", eta=0.5, alpha=0.0, b=0.0,

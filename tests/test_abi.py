@@ -67,6 +67,35 @@ def test_workspace_size_and_validation():
     assert "4 GiB" in str(e.value)
 
 
+def test_step_path_selection():
+    import paper_2103_04081_amd as P
+    # B beyond the persistent kernel: AUTO plans the grid step, whose
+    # workspace adds one R x I_max part per gather block
+    p_small = P.make_problem([300, 300, 300], 10, 256)
+    p_big = P.make_problem([300, 300, 300], 10, 65536)
+    o = P.make_options()
+    n_small = P.cpd_workspace_size(p_small, o)
+    n_big = P.cpd_workspace_size(p_big, o)
+    assert n_big - n_small >= 512 * 10 * 300 * 4
+    assert n_big - n_small < 512 * 10 * 300 * 4 + (1 << 16)
+    # the grid path can be asked for at any B; the persistent one only up to 4096
+    assert P.cpd_workspace_size(p_small, P.make_options(path="grid")) > n_small
+    with pytest.raises(P.CpdError) as e:
+        P.cpd_workspace_size(p_big, P.make_options(path="persistent"))
+    assert "4096" in str(e.value)
+    with pytest.raises(P.CpdError):
+        P.cpd_workspace_size(p_small, P.make_options(path=3))
+    with pytest.raises(P.CpdError) as e:
+        P.cpd_workspace_size(p_big, P.make_options(ksplit=[2, 0, 0]))
+    assert "grid" in str(e.value)
+    with pytest.raises(P.CpdError):
+        P.cpd_workspace_size(P.make_problem([300, 300, 300], 10, P.cpdmi.MAX_BATCH + 1), o)
+    # batched members and served requests use the persistent step
+    with pytest.raises(P.CpdError) as e:
+        P.cpd_batch_workspace_size([p_small, p_big], [o, o])
+    assert "persistent" in str(e.value)
+
+
 def test_ksplit_option_validation():
     import paper_2103_04081_amd as P
     p = P.make_problem([40, 300, 33], 10, 256)

@@ -31,6 +31,10 @@ CASES = [
     # long modes: waves own several row tiles each (the unsplit contraction)
     ((300, 20, 17), 6, 40, "euclidean", "f32"),
     ((530, 12, 10), 5, 30, "leverage", "bf16"),
+    # three rank tiles with more than 96 fibres: every chunk of the fibre
+    # range is a power-of-two number of K-steps
+    ((64, 48, 50), 40, 200, "euclidean", "f32"),
+    ((64, 48, 50), 40, 200, "euclidean", "bf16"),
 ]
 IDS = [f"{'x'.join(map(str, c[0]))}-R{c[1]}-B{c[2]}-{c[3]}-{c[4]}" for c in CASES]
 
