@@ -87,6 +87,12 @@ def parse():
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving section (profiling)")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--no-grid", action="store_true", help="skip the large-batch grid sweep")
+    ap.add_argument("--grid-only", action="store_true",
+                    help="run only the large-batch grid sweep (profiling)")
+    ap.add_argument("--grid-b", default="4096,16384,65536,131072,262144",
+                    help="mini-batch sizes of the grid sweep")
+    ap.add_argument("--grid-steps", type=int, default=100)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MiB (a "
                          "known-size kernel to scale hardware byte counters)")
@@ -136,6 +142,9 @@ def main():
     w = ci.workload(2)
     dims, R, B = w["dims"], w["R"], w["B"]
     X32 = np.asfortranarray(w["X"].astype(np.float32))
+    if args.grid_only:
+        print(json.dumps({"grid_sweep": grid_sweep(w, X32, args)}), flush=True)
+        return
 
     def make(sampler, seed=w["seed"]):
         return P.Decomposition(X32, w["A0"], B=B, sampler=sampler, rule="adagrad", eta=ETA,
@@ -175,6 +184,8 @@ def main():
         extra["time_to_fit"] = time_to_fit(make, target=0.99, every=25, max_steps=40000)
     if not args.no_batch:
         extra["batch"] = batch_bench(args.batch_count, seq=not args.no_seq)
+    if not args.no_grid:
+        extra["grid_sweep"] = grid_sweep(w, X32, args)
     if not args.no_variance:
         extra["variance"] = variance_study()
     if not args.no_serve:
@@ -405,6 +416,45 @@ def variance_study(steps=1000, every=100, B=18):
         out[f"data_{'ii' if which == 2 else 'iii'}_eval_gbps"] = nbytes / el / 1e9
         dec.close()
     return out
+
+
+def grid_sweep(w, X32, args):
+    """The same 300^3 FP32 tensor and R, with mini-batches far beyond one
+    workgroup: the grid step (three launches per step over the whole GPU),
+    timed with HIP events on the handle's stream, K steps after 19 warm-up
+    steps.  Uniform sampling reads fibres spread over the whole copy;
+    Euclidean sampling of this skewed tensor concentrates on few fibres.
+    GB/s are algorithmic bytes per step (fibres, sampled factor rows, A and
+    S read and write, CDF) over the step time."""
+    import torch
+
+    import paper_2103_04081_amd as P
+    dims, R = w["dims"], w["R"]
+    rows = []
+    for sampler in ("uniform", "euclidean"):
+        for B in [int(b) for b in args.grid_b.split(",") if b]:
+            dec = P.Decomposition(X32, w["A0"], B=B, sampler=sampler, rule="adagrad", eta=ETA,
+                                  storage="f32", seed=w["seed"], path="grid")
+            dec.step(19)  # builds and replays the 16-step graph once
+            dec.sync()
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(dec.stream)
+            dec.step(args.grid_steps)
+            ev1.record(dec.stream)
+            ev1.synchronize()
+            dec.sync()
+            ms = ev0.elapsed_time(ev1) / args.grid_steps
+            sb = step_bytes(dims, R, B, 4)
+            rows.append({"sampler": sampler, "B": B, "ms_per_step": ms,
+                         "steps_per_s": 1e3 / ms, "fibres_per_s": B * 1e3 / ms,
+                         "bytes_per_step": sb, "gbps": sb / ms / 1e6,
+                         "hbm_frac": sb / ms / 1e6 / 8000.0, "fit_after": dec.fit()})
+            dec.close()
+    return {"workload": "300x300x300 FP32 tensor of the main workload, R=10, AdaGrad "
+                        f"eta={ETA}; grid step (CPD_PATH_GRID), {args.grid_steps} timed steps",
+            "rows": rows}
 
 
 def time_to_fit(make, target, every, max_steps):

@@ -289,7 +289,14 @@ struct cpd_handle {
   int32_t* d_mode;      // scratch int in the state block
   int32_t* d_fitmap;    // fit block tables in the workspace
   FitPlan fit;
+  // grid path: kGridGraphSteps steps captured once (on a private stream,
+  // since the handle's may be the null stream) and replayed by cpd_step
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
+
+static constexpr int kGridGraphSteps = 16;
 
 // The distributions of every mode from the current factors.
 static hipError_t refresh_all(cpd_handle* h) {
@@ -313,10 +320,60 @@ static WideArgs wide_args(cpd_handle* h, int op) {
 static hipError_t wide_finish(cpd_handle* h, const WideArgs& a) {
   int imax = 0;
   for (int k = 0; k < h->p.N; ++k) imax = std::max(imax, h->p.dims[k]);
-  hipError_t e = launch_wide_update(h->d_desc, a.part, h->plan.wide_blocks, a.info, imax * h->p.R,
-                                    h->stream);
+  hipError_t e = launch_wide_update(h->d_desc, a.part, h->plan.wide_blocks, a.info,
+                                    imax * h->p.R, h->stream);
   if (e != hipSuccess || h->o.sampler == CPD_SAMPLER_UNIFORM) return e;
   return launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, a.info, -2, h->stream);
+}
+
+static hipError_t wide_steps(cpd_handle* h, int64_t nsteps, hipStream_t stream) {
+  const WideArgs a = wide_args(h, OP_STEP);
+  int imax = 0;
+  for (int k = 0; k < h->p.N; ++k) imax = std::max(imax, h->p.dims[k]);
+  for (int64_t i = 0; i < nsteps; ++i) {
+    hipError_t e = launch_wide_gather(h->d_desc, h->desc.RT, h->o.storage, h->plan.wide_blocks,
+                                      h->plan.gather_lds, a, stream);
+    if (e == hipSuccess)
+      e = launch_wide_update(h->d_desc, a.part, h->plan.wide_blocks, a.info, imax * h->p.R,
+                             stream);
+    if (e == hipSuccess && h->o.sampler != CPD_SAMPLER_UNIFORM)
+      e = launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, a.info, -2, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static cpd_status build_step_graph(cpd_handle* h) {
+  hipError_t e = hipSuccess;
+  if (!h->cap) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  const hipError_t e1 = wide_steps(h, kGridGraphSteps, h->cap);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(h->cap, &g);
+  if (e1 != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(e1 != hipSuccess ? e1 : e, "graph capture");
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  h->graph = g;
+  h->exec = x;
+  return CPD_OK;
+}
+
+static void release_graph(cpd_handle* h) {
+  if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  h->exec = nullptr;
+  h->graph = nullptr;
+  h->cap = nullptr;
 }
 
 static cpd_status read_state(cpd_handle* h, ChainState* st) {
@@ -448,6 +505,10 @@ cpd_status cpd_init(const cpd_problem* p, const cpd_options* o, const void* X, i
     h->d_fitmap = (int32_t*)(h->ws + w.fitmap);
     e = hipMemcpyAsync(h->d_fitmap, fitmap, sizeof fitmap, hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) return fail(e, "hipMemcpyAsync(fit table)");
+    if (w.grid) {
+      e = prepare_wide_kernels(h->desc.RT, o->storage);
+      if (e != hipSuccess) return fail(e, "grid kernel attributes");
+    }
     e = refresh_all(h);
     if (e != hipSuccess) return fail(e, "refresh kernel");
     e = launch_fit(h->d_desc, h->d_fitmap, 1, h->fit, o->storage, false, h->stream);
@@ -504,13 +565,21 @@ cpd_status cpd_step(cpd_handle* h, int64_t nsteps) {
   cpd_status s = set_device(h);
   if (s != CPD_OK) return s;
   if (h->plan.grid) {
-    const WideArgs a = wide_args(h, OP_STEP);
-    for (int64_t i = 0; i < nsteps; ++i) {
-      hipError_t e = launch_wide_gather(h->d_desc, h->desc.RT, h->o.storage, h->plan.wide_blocks,
-                                        h->plan.gather_lds, a, h->stream);
-      if (e == hipSuccess) e = wide_finish(h, a);
-      if (e != hipSuccess) return hip_fail(e, "grid step kernels");
+    // whole groups of steps as graph replays (three launches per step would
+    // otherwise be bound by the host), the rest launched directly
+    int64_t done = 0;
+    if (nsteps >= kGridGraphSteps) {
+      if (!h->exec) {
+        s = build_step_graph(h);
+        if (s != CPD_OK) return s;
+      }
+      for (; done + kGridGraphSteps <= nsteps; done += kGridGraphSteps) {
+        hipError_t e = hipGraphLaunch(h->exec, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      }
     }
+    hipError_t e = wide_steps(h, nsteps - done, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "grid step kernels");
     return CPD_OK;
   }
   const int64_t chunk = (int64_t)1 << 20;
@@ -736,6 +805,7 @@ cpd_status cpd_destroy(cpd_handle* h) {
   if (!h) return CPD_OK;
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
+  release_graph(h);
   delete h;
   return CPD_OK;
 }

@@ -279,10 +279,11 @@ __host__ __device__ inline LdsPlan lds_plan(int N, const int32_t* dims, int R, i
 // ---------------------------------------------------------------------------
 constexpr int kWideFibresMax = 512;
 
-// Fibres per block of the gather kernel for mini-batch B: about 512 blocks
-// (two per CU) while the slices stay within [128, 512] fibres.
+// Fibres per block of the gather kernel for mini-batch B: about 256 blocks
+// while the slices stay within [128, 512] fibres (measured on 300-element
+// fibres: fewer, longer slices win up to 512 fibres, more blocks beyond).
 inline int wide_fibres(int B) {
-  int fb = (int)round_up((B + 511) / 512, kFibrePad);
+  int fb = (int)round_up((B + 255) / 256, kFibrePad);
   if (fb < kFibrePad) fb = kFibrePad;
   if (fb > kWideFibresMax) fb = kWideFibresMax;
   return fb;

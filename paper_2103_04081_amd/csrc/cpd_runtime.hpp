@@ -30,16 +30,19 @@ FitPlan plan_fit(const ChainDesc* host_descs, int nchains, int32_t* tables);
 hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_tables, int nchains,
                       const FitPlan& fp, int dtype, bool inner, hipStream_t stream);
 
-// Grid-wide step (wide_step.hip).  Gather: nblocks slices of a.fb fibres;
-// update: the parts of every entry of mode n summed and applied (launched
-// over max_rows * R entries); refresh: the CDF of mode `mode` (-1: every
+// Grid-wide step (wide_step.hip).  Gather: nblocks slices of a.fb fibres,
+// one part of -G^T each; update: the parts of every entry of mode n summed
+// and applied (launched over max_rows * R entries); refresh: the CDF of mode `mode` (-1: every
 // mode, -2: the mode in info).
 hipError_t launch_wide_gather(const ChainDesc* d_desc, int rt, int dtype, int nblocks,
                               size_t lds_bytes, const WideArgs& a, hipStream_t stream);
-hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nparts,
+hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nblocks,
                               const WideInfo* info, int max_entries, hipStream_t stream);
 hipError_t launch_wide_refresh(const ChainDesc* d_desc, int rt, size_t lds_bytes,
                                const WideInfo* info, int mode, hipStream_t stream);
+// Sets the dynamic-LDS limits of the grid kernels for (rt, dtype); called
+// before any of them is captured into a graph.
+hipError_t prepare_wide_kernels(int rt, int dtype);
 
 // Offsets of every region of one decomposition's workspace.
 struct WsPlan {

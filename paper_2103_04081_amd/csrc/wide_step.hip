@@ -22,7 +22,8 @@
 
 namespace cpdmi {
 
-constexpr int kUpdWaves = 16;  // waves of an update block (64 entries each)
+constexpr int kUpdWaves = 16;    // waves of an update block
+constexpr int kUpdEntries = 16;  // entries of A^(n) per update block
 
 template <int RT, bool BF16>
 __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __restrict__ dp,
@@ -54,41 +55,29 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   S.ms = S.nd = S.nblk = S.has_sbuf = S.has_fac = 0;
   int32_t* misc = S.misc();
   const int64_t t = a.op == OP_SAMPLE ? (int64_t)a.sample_t : st->t;
-  // misc: [0] stop (sticky error before this launch), [1] error, [3] mode;
-  // one thread reads the status so that the whole block agrees on it
-  if (tid == 0) {
-    misc[0] = a.op != OP_SAMPLE && st->status != 0;
-    misc[1] = 0;
-    int o = 0;
-    for (int k = 0; k < N; ++k) {
-      S.coff()[k] = o;
-      o += dp->dims[k];
-    }
-    int n;
-    if (a.op == OP_REPLAY) {
-      n = a.replay_mode;
-    } else if (a.force_mode1) {
-      n = a.force_mode1 - 1;
-    } else {
-      uint64_t w0[4];
-      philox4x64_10((uint64_t)t, 0, 0, 0, dp->key0, dp->key1, w0);
-      n = (int)mulhi_u64(w0[0], (uint64_t)N);
-    }
-    misc[3] = n;
+  // One phase before the first barrier: the first CDF values are loaded into
+  // registers, the Philox blocks of this slice's draws (which do not depend
+  // on the mode) are computed while they are in flight, then the values are
+  // stored.  The last thread draws the mode and reads the sticky status
+  // (misc: [0] stop, [1] error, [3] mode), so the whole block agrees on them.
+  int sumdims = 0;
+  for (int k = 0; k < N; ++k) sumdims += dp->dims[k];
+  auto cdf_at = [&](int e) {
+    int k = 0, o = 0;
+    while (e >= o + dp->dims[k]) o += dp->dims[k++];
+    return gmem(dp->C[k])[e - o];
+  };
+  constexpr int kCdfRegs = 4;
+  double cv[kCdfRegs];
+#pragma unroll
+  for (int j = 0; j < kCdfRegs; ++j) {
+    const int e = tid + j * kBlock;
+    cv[j] = e < sumdims ? cdf_at(e) : 0.0;
   }
-  __syncthreads();
-  if (misc[0]) return;
-  const int n = uniform_int(misc[3]);
-  for (int k = 0; k < N; ++k) {
-    const CPD_GLOBAL double* Cg = gmem(dp->C[k]);
-    double* Cl = S.cdf() + S.coff()[k];
-    for (int i = tid; i < dp->dims[k]; i += kBlock) Cl[i] = Cg[i];
-  }
-  // ---- draws of this slice: draw d = 1 + slot * B + f uses word d % 4 of
-  // the Philox block (t, d / 4) -----------------------------------------------
   uint64_t* words = S.words();
   const int nwb = P.nwb;
   if (a.op != OP_REPLAY) {
+    // draw d = 1 + slot * B + f uses word d % 4 of the Philox block (t, d / 4)
     for (int e = tid; e < nm1 * nwb; e += kBlock) {
       const int sl = e / nwb, j = e - sl * nwb;
       const int64_t dfirst = 1 + (int64_t)sl * B + f0;
@@ -103,7 +92,36 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
       }
     }
   }
+  if (tid == kBlock - 1) {
+    misc[0] = a.op != OP_SAMPLE && st->status != 0;
+    misc[1] = 0;
+    int o = 0;
+    for (int k = 0; k < N; ++k) {
+      S.coff()[k] = o;
+      o += dp->dims[k];
+    }
+    int nd;
+    if (a.op == OP_REPLAY) {
+      nd = a.replay_mode;
+    } else if (a.force_mode1) {
+      nd = a.force_mode1 - 1;
+    } else {
+      uint64_t w0[4];
+      philox4x64_10((uint64_t)t, 0, 0, 0, dp->key0, dp->key1, w0);
+      nd = (int)mulhi_u64(w0[0], (uint64_t)N);
+    }
+    misc[3] = nd;
+  }
+  // the CDFs of all modes, back to back in mode order
+#pragma unroll
+  for (int j = 0; j < kCdfRegs; ++j) {
+    const int e = tid + j * kBlock;
+    if (e < sumdims) S.cdf()[e] = cv[j];
+  }
+  for (int e = tid + kCdfRegs * kBlock; e < sumdims; e += kBlock) S.cdf()[e] = cdf_at(e);
   __syncthreads();
+  if (misc[0]) return;
+  const int n = uniform_int(misc[3]);
   for (int e = tid; e < nm1 * nf; e += kBlock) {
     const int sl = e / nf, f = e - sl * nf;
     const int k = sl < n ? sl : sl + 1;
@@ -204,9 +222,6 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
     a.info->t = t;
     a.info->n = n;
   }
-  __syncthreads();
-  // ---- this slice's Gs -----------------------------------------------------
-  compute_gs<RT>(S);
   // ---- this slice's -G^T, per 16-column tile of the I_n x R output ---------
   //   A operand: lane l holds WH[f0 + l/16][rt*16 + l%16]           (LDS)
   //   B operand: lane l holds X_s[f0 + l/16][col0 + (l%16)*VW + v]   (HBM)
@@ -217,6 +232,9 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   const int SW = 16 * VW;
   const int nst = (In + SW - 1) / SW;
   const int nck = S.bpad / (4 * U);
+  // wave w owns tiles w, w + 8, ... and walks each over all the slice's
+  // fibres (long runs of loads in flight per wave measured faster than
+  // splitting the fibre range over waves or walking the tiles chunk by chunk)
   const int nitems = wave < nst ? (nst - 1 - wave) / kWaves + 1 : 0;
   const float* __restrict__ whtc = S.wht();
   const uint32_t* __restrict__ rowb = S.rowb();
@@ -226,11 +244,15 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   const int rp16 = S.rp16;
 
   f4 acc[RT][VW], acc2[RT][VW];
+  // two register buffers of fibre values, each with the A^(n) entries of the
+  // -Gs A^(n)T term, loaded with the last chunk of a tile
   float xa[U][VW], xb[U][VW];
-  auto load = [&](float (&x)[U][VW], int c) {
+  float pa[4 * RT][VW], pb[4 * RT][VW];
+  auto load = [&](float (&x)[U][VW], float (&pA)[4 * RT][VW], int c) {
     const int it = c / nck;
     const int stl = wave + it * kWaves;
-    const int kq0 = (c - it * nck) * (U / 4);  // first group of four K-steps
+    const int ci = c - it * nck;
+    const int kq0 = ci * (U / 4);  // first group of four K-steps
     const uint32_t colb = (uint32_t)((stl * SW + cl * VW) * (BF16 ? 2 : 4));
 #pragma unroll
     for (int u4 = 0; u4 < U / 4; ++u4) {
@@ -249,29 +271,35 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
         }
       }
     }
+    if (ci == nck - 1) {
+      // rank columns past R and rows past I_n read as zero
+      const int col0 = stl * SW;
+#pragma unroll
+      for (int kk = 0; kk < 4 * RT; ++kk) {
+        const int s = 4 * kk + fl;
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+          const int i = col0 + cl * VW + v;
+          pA[kk][v] = (s < R && i < In) ? An[(int64_t)i * R + s] : 0.f;
+        }
+      }
+    }
   };
-  auto epilogue = [&](int stl) {
+  auto epilogue = [&](int stl, const float (&pA)[4 * RT][VW]) {
     const int col0 = stl * SW;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int v = 0; v < VW; ++v) acc[rt][v] += acc2[rt][v];
-    // -Gs A^(n)T: rank columns past R and rows past I_n read as zero
 #pragma unroll
     for (int kk = 0; kk < 4 * RT; ++kk) {
       const int s = 4 * kk + fl;
-      float bA[VW];
-#pragma unroll
-      for (int v = 0; v < VW; ++v) {
-        const int i = col0 + cl * VW + v;
-        bA[v] = (s < R && i < In) ? An[(int64_t)i * R + s] : 0.f;
-      }
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         const float g = -S.gs()[(rt * 16 + cl) * rp16 + s];
 #pragma unroll
         for (int v = 0; v < VW; ++v)
-          acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, bA[v], acc[rt][v], 0, 0, 0);
+          acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, pA[kk][v], acc[rt][v], 0, 0, 0);
       }
     }
 #pragma unroll
@@ -285,7 +313,7 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
           if (r < R && i < In) part[(int64_t)r * In + i] = acc[rt][v][q];
         }
   };
-  auto compute = [&](const float (&x)[U][VW], int c) {
+  auto compute = [&](const float (&x)[U][VW], const float (&pA)[4 * RT][VW], int c) {
     const int it = c / nck;
     const int ci = c - it * nck;
     const int kq0 = ci * (U / 4);
@@ -317,63 +345,77 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
             acc2[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                 wa[u4][rt][j + 1], x[4 * u4 + j + 1][v], acc2[rt][v], 0, 0, 0);
           }
-    if (ci == nck - 1) epilogue(wave + it * kWaves);
+    if (ci == nck - 1) epilogue(wave + it * kWaves, pA);
   };
   const int total = nitems * nck;
-  if (total > 0) {
-    load(xa, 0);
-    for (int c = 0; c < total; c += 2) {
-      if (c + 1 < total) load(xb, c + 1);
-      compute(xa, c);
-      if (c + 2 < total) load(xa, c + 2);
-      if (c + 1 < total) compute(xb, c + 1);
-    }
+  __syncthreads();
+  // the first chunk's fibre loads are in flight while this slice's Gs forms
+  if (total > 0) load(xa, pa, 0);
+  compute_gs<RT>(S);
+  for (int c = 0; c < total; c += 2) {
+    if (c + 1 < total) load(xb, pb, c + 1);
+    compute(xa, pa, c);
+    if (c + 2 < total) load(xa, pa, c + 2);
+    if (c + 1 < total) compute(xb, pb, c + 1);
   }
 }
 
-// Entry e = r * I_n + i of -G^T: the block parts summed in a fixed order
-// (each wave a contiguous range of blocks, then the waves in order), then
-// the step rule on A^(n)(i, r).
+// Entry e = r * I_n + i of -G^T: the block parts summed in a fixed order,
+// then the step rule on A^(n)(i, r).  A block takes 16 entries; its 64 lane
+// groups of 16 lanes (four per wave) sum the parts g, g + 64, g + 128, ...
+// (one 64-byte row segment per part and lane group), then one thread per
+// entry adds the 64 group sums in order.
 __global__ void __launch_bounds__(64 * kUpdWaves) wide_update_kernel(
-    const ChainDesc* __restrict__ dp, const float* __restrict__ part, int nparts,
+    const ChainDesc* __restrict__ dp, const float* __restrict__ part, int nblocks,
     const WideInfo* __restrict__ info) {
-  __shared__ float red[kUpdWaves][64];
-  __shared__ int stop;
+  constexpr int kGroups = 4 * kUpdWaves;
+  __shared__ float red[kGroups][kUpdEntries + 1];
+  __shared__ int sh_stop, sh_n;
+  __shared__ int64_t sh_t;
   ChainState* st = dp->state;
-  if (threadIdx.x == 0) stop = st->status != 0;
+  if (threadIdx.x == 0) {
+    sh_stop = st->status != 0;
+    sh_n = info->n;
+    sh_t = info->t;
+  }
   __syncthreads();
-  if (stop) return;
+  if (sh_stop) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int n = info->n;
-  const int64_t t = info->t;
+  const int g = wave * 4 + (lane >> 4), ec = lane & 15;
+  const int n = sh_n;
+  const int64_t t = sh_t;
   const int In = dp->dims[n], R = dp->R, E = In * R;
-  const int e = blockIdx.x * 64 + lane;
-  const int b0 = wave * nparts / kUpdWaves, b1 = (wave + 1) * nparts / kUpdWaves;
+  const int nparts = nblocks;  // one part per gather block
+  const int e = blockIdx.x * kUpdEntries + ec;
+  // the entry this thread updates: its A and S values are loaded with the
+  // parts
+  const int e1 = blockIdx.x * kUpdEntries + (int)threadIdx.x;
+  const bool upd = threadIdx.x < kUpdEntries && e1 < E;
+  const int64_t ai = upd ? (int64_t)(e1 % In) * R + e1 / In : 0;
+  CPD_GLOBAL float* An = gmem(dp->A[n]);
+  CPD_GLOBAL float* Sn = gmem(dp->S[n]);
+  const UpdateParams up = update_params(dp, (uint64_t)t);
+  const float a_old = upd ? An[ai] : 0.f;
+  float sacc = (upd && up.ada) ? Sn[ai] : 0.f;
   float s = 0.f;
   if (e < E) {
     const CPD_GLOBAL float* pp = gmem(part) + e;
-    int b = b0;
-    for (; b + 8 <= b1; b += 8) {
+    int b = g;
+    for (; b + 7 * kGroups < nparts; b += 8 * kGroups) {
       float v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = pp[(int64_t)(b + j) * E];
+      for (int j = 0; j < 8; ++j) v[j] = pp[(int64_t)(b + j * kGroups) * E];
 #pragma unroll
       for (int j = 0; j < 8; ++j) s = s + v[j];
     }
-    for (; b < b1; ++b) s = s + pp[(int64_t)b * E];
+    for (; b < nparts; b += kGroups) s = s + pp[(int64_t)b * E];
   }
-  red[wave][lane] = s;
+  red[g][ec] = s;
   __syncthreads();
-  if (wave == 0 && e < E) {
-    float m = red[0][lane];
-    for (int w = 1; w < kUpdWaves; ++w) m = m + red[w][lane];
-    const int r = e / In, i = e - r * In;
-    const int64_t ai = (int64_t)i * R + r;
-    const UpdateParams up = update_params(dp, (uint64_t)t);
-    CPD_GLOBAL float* An = gmem(dp->A[n]);
-    CPD_GLOBAL float* Sn = gmem(dp->S[n]);
-    float sacc = up.ada ? Sn[ai] : 0.f;
-    const float an = update_entry(up, An[ai], -m, sacc);
+  if (upd) {
+    float m = red[0][threadIdx.x];
+    for (int q = 1; q < kGroups; ++q) m = m + red[q][threadIdx.x];
+    const float an = update_entry(up, a_old, -m, sacc);
     if (up.ada) Sn[ai] = sacc;
     An[ai] = an;
     if (!isfinite(an)) st->status = CPD_E_DIVERGED;
@@ -430,8 +472,7 @@ __global__ void __launch_bounds__(kBlock) wide_refresh_kernel(const ChainDesc* _
 }
 
 template <int RT, bool BF16>
-static hipError_t gather_rt(const ChainDesc* d, int nblocks, size_t lds, const WideArgs& a,
-                            hipStream_t s) {
+static hipError_t gather_attr() {
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)wide_gather_kernel<RT, BF16>,
@@ -439,6 +480,41 @@ static hipError_t gather_rt(const ChainDesc* d, int nblocks, size_t lds, const W
     if (e != hipSuccess) return e;
     attr_set = true;
   }
+  return hipSuccess;
+}
+
+template <int RT>
+static hipError_t refresh_attr() {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)wide_refresh_kernel<RT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  return hipSuccess;
+}
+
+template <int RT>
+static hipError_t prepare_rt(int dtype) {
+  hipError_t e = dtype == CPD_BF16 ? gather_attr<RT, true>() : gather_attr<RT, false>();
+  return e == hipSuccess ? refresh_attr<RT>() : e;
+}
+
+hipError_t prepare_wide_kernels(int rt, int dtype) {
+  switch (rt) {
+    case 1: return prepare_rt<1>(dtype);
+    case 2: return prepare_rt<2>(dtype);
+    case 3: return prepare_rt<3>(dtype);
+    default: return prepare_rt<4>(dtype);
+  }
+}
+
+template <int RT, bool BF16>
+static hipError_t gather_rt(const ChainDesc* d, int nblocks, size_t lds, const WideArgs& a,
+                            hipStream_t s) {
+  hipError_t e = gather_attr<RT, BF16>();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((wide_gather_kernel<RT, BF16>), dim3(nblocks), dim3(kBlock), lds, s, d, a);
   return hipGetLastError();
 }
@@ -458,24 +534,19 @@ hipError_t launch_wide_gather(const ChainDesc* d_desc, int rt, int dtype, int nb
   }
 }
 
-hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nparts,
+hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nblocks,
                               const WideInfo* info, int max_entries, hipStream_t stream) {
-  const int nblocks = (max_entries + 63) / 64;
-  hipLaunchKernelGGL(wide_update_kernel, dim3(nblocks), dim3(64 * kUpdWaves), 0, stream, d_desc,
-                     part, nparts, info);
+  const int grid = (max_entries + kUpdEntries - 1) / kUpdEntries;
+  hipLaunchKernelGGL(wide_update_kernel, dim3(grid), dim3(64 * kUpdWaves), 0, stream, d_desc,
+                     part, nblocks, info);
   return hipGetLastError();
 }
 
 template <int RT>
 static hipError_t refresh_rt(const ChainDesc* d, size_t lds, const WideInfo* info, int mode,
                              hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)wide_refresh_kernel<RT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = refresh_attr<RT>();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(wide_refresh_kernel<RT>, dim3(1), dim3(kBlock), lds, s, d, info, mode);
   return hipGetLastError();
 }

@@ -160,3 +160,22 @@ def test_grid_variance_and_state_round_trip():
     g.close()
     g2.close()
     p.close()
+
+
+def test_grid_graph_replay_equals_single_launches():
+    """cpd_step with 16 or more steps replays a captured graph of 16 steps;
+    the iterates are those of the same steps launched one by one."""
+    _announce("grid_graph")
+    prob = problem((37, 45, 53), 7)
+    for sampler in ("euclidean", "uniform"):
+        g = gpu_decomposition(prob, 300, sampler=sampler, path="grid")
+        h = gpu_decomposition(prob, 300, sampler=sampler, path="grid")
+        g.step(40)
+        g.step(17)
+        for _ in range(57):
+            h.step(1)
+        assert g.t == 57 and h.t == 57
+        for a, b in zip(g.factors(), h.factors()):
+            np.testing.assert_array_equal(a, b)
+        g.close()
+        h.close()
