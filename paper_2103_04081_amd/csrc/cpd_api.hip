@@ -129,7 +129,7 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
     w->wide_info = off;
     off = align_up(off + sizeof(WideInfo));
     w->wide_part = off;
-    off = align_up(off + sizeof(float) * (size_t)w->wide_blocks * p->R * imax);
+    off = align_up(off + sizeof(float) * (size_t)w->wide_blocks * kWideMaxParts * p->R * imax);
   }
   for (int k = 0; k < p->N; ++k) {
     const size_t fb = sizeof(float) * (size_t)p->dims[k] * p->R;
@@ -320,8 +320,8 @@ static WideArgs wide_args(cpd_handle* h, int op) {
 static hipError_t wide_finish(cpd_handle* h, const WideArgs& a) {
   int imax = 0;
   for (int k = 0; k < h->p.N; ++k) imax = std::max(imax, h->p.dims[k]);
-  hipError_t e = launch_wide_update(h->d_desc, a.part, h->plan.wide_blocks, a.info,
-                                    imax * h->p.R, h->stream);
+  hipError_t e = launch_wide_update(h->d_desc, a.part, h->plan.wide_blocks, h->plan.wide_fb,
+                                    a.info, imax * h->p.R, h->stream);
   if (e != hipSuccess || h->o.sampler == CPD_SAMPLER_UNIFORM) return e;
   return launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, a.info, -2, h->stream);
 }
@@ -334,8 +334,8 @@ static hipError_t wide_steps(cpd_handle* h, int64_t nsteps, hipStream_t stream) 
     hipError_t e = launch_wide_gather(h->d_desc, h->desc.RT, h->o.storage, h->plan.wide_blocks,
                                       h->plan.gather_lds, a, stream);
     if (e == hipSuccess)
-      e = launch_wide_update(h->d_desc, a.part, h->plan.wide_blocks, a.info, imax * h->p.R,
-                             stream);
+      e = launch_wide_update(h->d_desc, a.part, h->plan.wide_blocks, h->plan.wide_fb, a.info,
+                             imax * h->p.R, stream);
     if (e == hipSuccess && h->o.sampler != CPD_SAMPLER_UNIFORM)
       e = launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, a.info, -2, stream);
     if (e != hipSuccess) return e;

@@ -289,6 +289,19 @@ inline int wide_fibres(int B) {
   return fb;
 }
 
+// Fibre-range split of a gather block's contraction for a mode of nst
+// output tiles: with fewer tiles than waves, the 8 waves form 8 / kp tile
+// groups times kp parts of the slice's nck chunks (so every wave has work);
+// kp = 1 otherwise (one wave per tile over all the fibres measured faster
+// than any split once every wave has a tile).  Each (block, part) writes its
+// own part of -G^T.
+constexpr int kWideMaxParts = 8;
+__host__ __device__ inline int wide_kparts(int nst, int nck) {
+  int kp = 1;
+  while (kp < kWideMaxParts && nst * kp * 2 <= kWaves && kp * 2 <= nck) kp *= 2;
+  return kp;
+}
+
 // Mode and step of the step in flight, written by the gather kernel for the
 // update and refresh kernels that follow it on the stream.
 struct WideInfo {

@@ -232,15 +232,24 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   const int SW = 16 * VW;
   const int nst = (In + SW - 1) / SW;
   const int nck = S.bpad / (4 * U);
-  // wave w owns tiles w, w + 8, ... and walks each over all the slice's
-  // fibres (long runs of loads in flight per wave measured faster than
-  // splitting the fibre range over waves or walking the tiles chunk by chunk)
-  const int nitems = wave < nst ? (nst - 1 - wave) / kWaves + 1 : 0;
+  // wave w owns tiles tg, tg + 8/kp, ... of its tile group and walks each
+  // over its part of the slice's fibres (long runs of loads in flight per
+  // wave measured faster than walking the tiles chunk by chunk).  Every
+  // block splits its chunks as a full slice would, so the part count is the
+  // same for all blocks; waves of a short last block may get no chunk.
+  const int nck_full = FB / (4 * U);
+  const int kp = wide_kparts(nst, nck_full);
+  const int tgn = kWaves / kp;
+  const int tg = wave % tgn, kpart = wave / tgn;
+  const int c0 = kpart * nck_full / kp;
+  const int c1 = min((kpart + 1) * nck_full / kp, nck);
+  const int nckw = c1 > c0 ? c1 - c0 : 0;
+  const int nitems = tg < nst ? (nst - 1 - tg) / tgn + 1 : 0;
   const float* __restrict__ whtc = S.wht();
   const uint32_t* __restrict__ rowb = S.rowb();
   const CPD_GLOBAL char* __restrict__ Xb = gmem((const char*)dp->X[n]);
   const CPD_GLOBAL float* An = gmem(dp->A[n]);
-  CPD_GLOBAL float* part = gmem(a.part) + (int64_t)blockIdx.x * R * In;
+  CPD_GLOBAL float* part = gmem(a.part) + ((int64_t)blockIdx.x * kp + kpart) * R * In;
   const int rp16 = S.rp16;
 
   f4 acc[RT][VW], acc2[RT][VW];
@@ -249,9 +258,9 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   float xa[U][VW], xb[U][VW];
   float pa[4 * RT][VW], pb[4 * RT][VW];
   auto load = [&](float (&x)[U][VW], float (&pA)[4 * RT][VW], int c) {
-    const int it = c / nck;
-    const int stl = wave + it * kWaves;
-    const int ci = c - it * nck;
+    const int it = c / nckw;
+    const int stl = tg + it * tgn;
+    const int ci = c0 + (c - it * nckw);
     const int kq0 = ci * (U / 4);  // first group of four K-steps
     const uint32_t colb = (uint32_t)((stl * SW + cl * VW) * (BF16 ? 2 : 4));
 #pragma unroll
@@ -271,8 +280,9 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
         }
       }
     }
-    if (ci == nck - 1) {
-      // rank columns past R and rows past I_n read as zero
+    if (ci == c1 - 1) {
+      // rank columns past R and rows past I_n read as zero (the first part
+      // adds the term)
       const int col0 = stl * SW;
 #pragma unroll
       for (int kk = 0; kk < 4 * RT; ++kk) {
@@ -280,7 +290,7 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
           const int i = col0 + cl * VW + v;
-          pA[kk][v] = (s < R && i < In) ? An[(int64_t)i * R + s] : 0.f;
+          pA[kk][v] = (kpart == 0 && s < R && i < In) ? An[(int64_t)i * R + s] : 0.f;
         }
       }
     }
@@ -314,10 +324,10 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
         }
   };
   auto compute = [&](const float (&x)[U][VW], const float (&pA)[4 * RT][VW], int c) {
-    const int it = c / nck;
-    const int ci = c - it * nck;
+    const int it = c / nckw;
+    const int ci = c0 + (c - it * nckw);
     const int kq0 = ci * (U / 4);
-    if (ci == 0) {
+    if (ci == c0) {
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -345,9 +355,25 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
             acc2[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                 wa[u4][rt][j + 1], x[4 * u4 + j + 1][v], acc2[rt][v], 0, 0, 0);
           }
-    if (ci == nck - 1) epilogue(wave + it * kWaves, pA);
+    if (ci == c1 - 1) epilogue(tg + it * tgn, pA);
   };
-  const int total = nitems * nck;
+  const int total = nitems * nckw;
+  if (nitems > 0 && nckw == 0) {
+    // a short last block: this part of every tile of the wave is zero
+    for (int it = 0; it < nitems; ++it) {
+      const int col0 = (tg + it * tgn) * SW;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < VW; ++v)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = rt * 16 + 4 * fl + q;
+            const int i = col0 + cl * VW + v;
+            if (r < R && i < In) part[(int64_t)r * In + i] = 0.f;
+          }
+    }
+  }
   __syncthreads();
   // the first chunk's fibre loads are in flight while this slice's Gs forms
   if (total > 0) load(xa, pa, 0);
@@ -366,7 +392,7 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
 // (one 64-byte row segment per part and lane group), then one thread per
 // entry adds the 64 group sums in order.
 __global__ void __launch_bounds__(64 * kUpdWaves) wide_update_kernel(
-    const ChainDesc* __restrict__ dp, const float* __restrict__ part, int nblocks,
+    const ChainDesc* __restrict__ dp, const float* __restrict__ part, int nblocks, int fb,
     const WideInfo* __restrict__ info) {
   constexpr int kGroups = 4 * kUpdWaves;
   __shared__ float red[kGroups][kUpdEntries + 1];
@@ -385,7 +411,10 @@ __global__ void __launch_bounds__(64 * kUpdWaves) wide_update_kernel(
   const int n = sh_n;
   const int64_t t = sh_t;
   const int In = dp->dims[n], R = dp->R, E = In * R;
-  const int nparts = nblocks;  // one part per gather block
+  // the parts the gather kernel wrote: wide_kparts of the mode per block
+  const int vw = dp->dtype == CPD_BF16 ? 2 : 1;
+  const int nparts =
+      nblocks * wide_kparts((In + 16 * vw - 1) / (16 * vw), fb / (4 * chunk_steps(vw, dp->RT)));
   const int e = blockIdx.x * kUpdEntries + ec;
   // the entry this thread updates: its A and S values are loaded with the
   // parts
@@ -430,7 +459,10 @@ __global__ void __launch_bounds__(kBlock) wide_refresh_kernel(const ChainDesc* _
                                                               const WideInfo* __restrict__ info,
                                                               int mode) {
   ChainState* st = dp->state;
-  if (mode == -2 && st->status != 0) return;
+  // status and mode loaded together (one round trip)
+  const int32_t status = st->status;
+  const int ninfo = mode == -2 ? info->n : 0;
+  if (mode == -2 && status != 0) return;
   const int tid = threadIdx.x;
   const int N = dp->N, R = dp->R;
   const RefreshPlan P = refresh_plan(N, dp->dims, R, RT);
@@ -455,7 +487,7 @@ __global__ void __launch_bounds__(kBlock) wide_refresh_kernel(const ChainDesc* _
     const int i = e / padc;
     mbuf[i * P.ms + R + (e - i * padc)] = 0.f;
   }
-  const int nb = mode >= 0 ? mode : (mode == -1 ? 0 : info->n);
+  const int nb = mode >= 0 ? mode : (mode == -1 ? 0 : ninfo);
   const int ne = mode == -1 ? N : nb + 1;
   int err = 0;
   for (int n = nb; n < ne && !err; ++n) {
@@ -534,11 +566,11 @@ hipError_t launch_wide_gather(const ChainDesc* d_desc, int rt, int dtype, int nb
   }
 }
 
-hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nblocks,
+hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nblocks, int fb,
                               const WideInfo* info, int max_entries, hipStream_t stream) {
   const int grid = (max_entries + kUpdEntries - 1) / kUpdEntries;
   hipLaunchKernelGGL(wide_update_kernel, dim3(grid), dim3(64 * kUpdWaves), 0, stream, d_desc,
-                     part, nblocks, info);
+                     part, nblocks, fb, info);
   return hipGetLastError();
 }
 

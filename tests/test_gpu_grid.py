@@ -179,3 +179,25 @@ def test_grid_graph_replay_equals_single_launches():
             np.testing.assert_array_equal(a, b)
         g.close()
         h.close()
+
+
+@pytest.mark.parametrize("dims,R,sampler,storage", [((20, 24, 22, 18), 12, "leverage", "bf16"),
+                                                    ((30, 31, 29), 6, "euclidean", "f32")])
+def test_grid_short_modes_split_fibre_range(dims, R, sampler, storage):
+    """Modes with fewer 16-row tiles than waves split each block's fibres
+    over the waves (several parts per block); B = 38405 makes slices of
+    256 fibres with a last block of 5, whose later parts are empty."""
+    _announce("grid_short_modes", dims, R, sampler, storage)
+    B = 38405
+    prob = problem(dims, R, storage=storage)
+    g = gpu_decomposition(prob, B, sampler=sampler, storage=storage, eta=0.3, path="grid")
+    orc = oracle_for(prob, B, sampler=sampler, eta=0.3)
+    for t in range(6):
+        n, idx, _ = g.sample(t)
+        orc.step(replay=(n, idx))
+        g.step(1)
+    A = g.factors()
+    err = max(rel(A[k], orc.A[k]) for k in range(len(dims)))
+    print(f"short modes, B = {B}: max rel err vs oracle {err:.3e}")
+    assert err <= 1e-5
+    g.close()
