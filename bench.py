@@ -464,9 +464,41 @@ def grid_sweep(w, X32, args):
                          "bytes_per_step": sb, "gbps": sb / ms / 1e6,
                          "hbm_frac": sb / ms / 1e6 / 8000.0, "fit_after": dec.fit()})
             dec.close()
+    # the 4-way workload in BF16 storage: 120^4 (207M entries), R = 20, SNR 30 dB,
+    # built on the device; 8-row output tiles per mode split each block's
+    # fibre range over two wave groups
+    import cpd_inputs as ci
+    spec4 = {"dims": (120, 120, 120, 120), "R": 20, "data_seed": 1003, "init_seed": 2003,
+             "snr_db": 30.0}
+    X4, A04 = ci.device_problem(spec4, "cuda")
+    rows4 = []
+    for sampler in ("uniform", "euclidean"):
+        for B in (65536, 262144):
+            dec = P.Decomposition(X4, A04, B=B, sampler=sampler, rule="adagrad", eta=1.0,
+                                  storage="bf16", seed=3003, path="grid")
+            dec.step(19)
+            dec.sync()
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(dec.stream)
+            dec.step(args.grid_steps)
+            ev1.record(dec.stream)
+            ev1.synchronize()
+            dec.sync()
+            ms = ev0.elapsed_time(ev1) / args.grid_steps
+            sb = step_bytes(list(spec4["dims"]), spec4["R"], B, 2)
+            rows4.append({"sampler": sampler, "B": B, "ms_per_step": ms, "steps_per_s": 1e3 / ms,
+                          "bytes_per_step": sb, "gbps": sb / ms / 1e6,
+                          "hbm_frac": sb / ms / 1e6 / 8000.0})
+            dec.close()
+    del X4
     return {"workload": "300x300x300 FP32 tensor of the main workload, R=10, AdaGrad "
                         f"eta={ETA}; grid step (CPD_PATH_GRID), {args.grid_steps} timed steps",
-            "rows": rows}
+            "rows": rows,
+            "workload_4way_bf16": "120^4 tensor (N(0,1) factors, SNR 30 dB, built on the device) "
+                                  "stored in BF16, R=20, AdaGrad eta=1.0; grid step",
+            "rows_4way_bf16": rows4}
 
 
 def time_to_fit(make, target, every, max_steps):
