@@ -5,6 +5,7 @@
 #include <string>
 
 #include "cpd_internal.hpp"
+#include "wide_internal.hpp"
 
 namespace cpdmi {
 

@@ -1,0 +1,122 @@
+// Host and device definitions of the grid-wide step (large mini-batches):
+// slice sizes, the fibre-range split of a gather block, the hand-over
+// between its three kernels and their LDS maps.
+#pragma once
+
+#include "cpd_internal.hpp"
+
+namespace cpdmi {
+
+// ---------------------------------------------------------------------------
+// Grid-wide step (large mini-batches): every block of the gather kernel
+// takes a slice of up to kWideFibresMax sampled fibres.
+// ---------------------------------------------------------------------------
+constexpr int kWideFibresMax = 512;
+
+// Fibres per block of the gather kernel for mini-batch B: about 256 blocks
+// while the slices stay within [128, 512] fibres (measured on 300-element
+// fibres: fewer, longer slices win up to 512 fibres, more blocks beyond).
+inline int wide_fibres(int B) {
+  int fb = (int)round_up((B + 255) / 256, kFibrePad);
+  if (fb < kFibrePad) fb = kFibrePad;
+  if (fb > kWideFibresMax) fb = kWideFibresMax;
+  return fb;
+}
+
+// Fibre-range split of a gather block's contraction for a mode of nst
+// output tiles: with fewer tiles than waves, the 8 waves form 8 / kp tile
+// groups times kp parts of the slice's nck chunks (so every wave has work);
+// kp = 1 otherwise (one wave per tile over all the fibres measured faster
+// than any split once every wave has a tile).  Each (block, part) writes its
+// own part of -G^T.
+constexpr int kWideMaxParts = 8;
+__host__ __device__ inline int wide_kparts(int nst, int nck) {
+  int kp = 1;
+  while (kp < kWideMaxParts && nst * kp * 2 <= kWaves && kp * 2 <= nck) kp *= 2;
+  return kp;
+}
+
+// Mode and step of the step in flight, written by the gather kernel for the
+// update and refresh kernels that follow it on the stream.
+struct WideInfo {
+  int64_t t;
+  int32_t n;
+  int32_t pad;
+};
+
+struct WideArgs {
+  int32_t op;           // OP_STEP, OP_SAMPLE or OP_REPLAY
+  int32_t replay_mode;  // OP_REPLAY: the mode
+  int32_t force_mode1;  // OP_STEP timing runs: 1 + the mode every step uses; 0 = drawn
+  int32_t fb;           // fibres per block (a multiple of kFibrePad)
+  uint64_t sample_t;
+  const int32_t* replay_idx;
+  int32_t* out_idx;
+  double* out_p;
+  int32_t* out_mode;
+  float* part;          // per block: -G^T, R x I_n (row r holds the I_n entries)
+  WideInfo* info;
+};
+
+// LDS map of the gather kernel (one slice of fb fibres).
+struct GatherPlan {
+  size_t cdf, idx, ratio, words, wf, rinv, rowoff, wht, gs, gsp, misc, total;
+  int nwb;  // Philox blocks per mode slot
+};
+
+__host__ __device__ inline GatherPlan gather_plan(int N, const int32_t* dims, int RT, int fb) {
+  GatherPlan p;
+  int sumdims = 0;
+  for (int k = 0; k < N; ++k) sumdims += dims[k];
+  const int nm1 = N - 1, rp16 = 16 * RT, t2 = RT * RT;
+  p.nwb = fb / 4 + 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (size_t)round_up((int64_t)bytes, 16);
+    return o;
+  };
+  p.cdf = take(sizeof(double) * sumdims);
+  p.idx = take(sizeof(int32_t) * (size_t)fb * nm1);
+  p.ratio = take(sizeof(double) * (size_t)fb * nm1);
+  p.words = take(sizeof(uint64_t) * 4 * (size_t)p.nwb * nm1);
+  p.wf = take(sizeof(float) * fb);
+  p.rinv = take(sizeof(float) * fb);
+  p.rowoff = take(sizeof(uint32_t) * fb);
+  p.wht = take(sizeof(float) * (size_t)fb * rp16);
+  p.gs = take(sizeof(float) * (size_t)rp16 * rp16);
+  p.gsp = take(sizeof(float) * 256 * (size_t)(t2 > kWaves ? t2 : kWaves));
+  p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
+  p.total = off;
+  return p;
+}
+
+// LDS map of the refresh kernel (the CDF of one mode at a time).
+struct RefreshPlan {
+  size_t cdf, mbuf, gram, part, red, wts, misc, total;
+  int ms, imax;
+};
+
+__host__ __device__ inline RefreshPlan refresh_plan(int N, const int32_t* dims, int R, int RT) {
+  RefreshPlan p;
+  p.imax = 0;
+  for (int k = 0; k < N; ++k) p.imax = dims[k] > p.imax ? dims[k] : p.imax;
+  p.ms = 16 * RT + 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (size_t)round_up((int64_t)bytes, 16);
+    return o;
+  };
+  p.cdf = take(sizeof(double) * p.imax);
+  p.mbuf = take(sizeof(float) * (size_t)p.imax * p.ms);
+  p.gram = take(sizeof(double) * (size_t)R * R);
+  p.part = take(sizeof(double) * kBlock);
+  p.red = take(sizeof(double) * 2 * kWaves);
+  p.wts = take(sizeof(double) * (size_t)p.imax);
+  p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
+  p.total = off;
+  return p;
+}
+
+}  // namespace cpdmi
