@@ -274,18 +274,19 @@ __device__ __forceinline__ int refresh_cdf(const ChainDesc* dp, const Smem& S, i
 //   B operand (4 x 16): lane l holds H[f0 + l/16][ct*16 + l%16]
 //   D (16 x 16): lane l, element q holds row 4*(l/16)+q, column l%16
 // ---------------------------------------------------------------------------
-template <int RT>
+template <int RT, int NT = kBlock>
 __device__ __forceinline__ void compute_gs(const Smem& S) {
+  constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = uniform_int(threadIdx.x >> 6);
   const int fl = lane >> 4, cl = lane & 15;
   constexpr int T2 = RT * RT;
-  constexpr int kparts = T2 >= kWaves ? 1 : kWaves / T2;
+  constexpr int kparts = T2 >= NW ? 1 : NW / T2;
   constexpr int items = T2 * kparts;
   const int nq = S.bpad / 16;  // groups of four K-steps
   const float* wht = S.wht();
   const float* rinv = S.rinv();
   float* gsp = S.gsp();
-  for (int it = wave; it < items; it += kWaves) {
+  for (int it = wave; it < items; it += NW) {
     const int tile = it % T2, kp = it / T2;
     const int rt = tile / RT, ct = tile % RT;
     const int q0 = kp * nq / kparts, q1 = (kp + 1) * nq / kparts;
@@ -304,7 +305,7 @@ __device__ __forceinline__ void compute_gs(const Smem& S) {
   }
   __syncthreads();
   const int rp16 = S.rp16;
-  for (int e = threadIdx.x; e < rp16 * rp16; e += kBlock) {
+  for (int e = threadIdx.x; e < rp16 * rp16; e += NT) {
     const int r = e / rp16, s2 = e - r * rp16;
     const int tile = (r >> 4) * RT + (s2 >> 4);
     float acc = 0.f;

@@ -12,6 +12,8 @@ namespace cpdmi {
 // takes a slice of up to kWideFibresMax sampled fibres.
 // ---------------------------------------------------------------------------
 constexpr int kWideFibresMax = 512;
+constexpr int kGatherThreads = 512;  // threads of a gather block
+constexpr int kGatherWaves = kGatherThreads / 64;
 
 // Fibres per block of the gather kernel for mini-batch B: about 256 blocks
 // while the slices stay within [128, 512] fibres (measured on 300-element
@@ -32,7 +34,7 @@ inline int wide_fibres(int B) {
 constexpr int kWideMaxParts = 8;
 __host__ __device__ inline int wide_kparts(int nst, int nck) {
   int kp = 1;
-  while (kp < kWideMaxParts && nst * kp * 2 <= kWaves && kp * 2 <= nck) kp *= 2;
+  while (kp < kWideMaxParts && nst * kp * 2 <= kGatherWaves && kp * 2 <= nck) kp *= 2;
   return kp;
 }
 
@@ -85,7 +87,7 @@ __host__ __device__ inline GatherPlan gather_plan(int N, const int32_t* dims, in
   p.rowoff = take(sizeof(uint32_t) * fb);
   p.wht = take(sizeof(float) * (size_t)fb * rp16);
   p.gs = take(sizeof(float) * (size_t)rp16 * rp16);
-  p.gsp = take(sizeof(float) * 256 * (size_t)(t2 > kWaves ? t2 : kWaves));
+  p.gsp = take(sizeof(float) * 256 * (size_t)(t2 > kGatherWaves ? t2 : kGatherWaves));
   p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
   p.total = off;
   return p;

@@ -26,7 +26,7 @@ constexpr int kUpdWaves = 16;    // waves of an update block
 constexpr int kUpdEntries = 16;  // entries of A^(n) per update block
 
 template <int RT, bool BF16>
-__global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __restrict__ dp,
+__global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const ChainDesc* __restrict__ dp,
                                                              WideArgs a) {
   ChainState* st = dp->state;
   const int tid = threadIdx.x;
@@ -71,14 +71,14 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   double cv[kCdfRegs];
 #pragma unroll
   for (int j = 0; j < kCdfRegs; ++j) {
-    const int e = tid + j * kBlock;
+    const int e = tid + j * kGatherThreads;
     cv[j] = e < sumdims ? cdf_at(e) : 0.0;
   }
   uint64_t* words = S.words();
   const int nwb = P.nwb;
   if (a.op != OP_REPLAY) {
     // draw d = 1 + slot * B + f uses word d % 4 of the Philox block (t, d / 4)
-    for (int e = tid; e < nm1 * nwb; e += kBlock) {
+    for (int e = tid; e < nm1 * nwb; e += kGatherThreads) {
       const int sl = e / nwb, j = e - sl * nwb;
       const int64_t dfirst = 1 + (int64_t)sl * B + f0;
       const int64_t c = (dfirst >> 2) + j;
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
       }
     }
   }
-  if (tid == kBlock - 1) {
+  if (tid == kGatherThreads - 1) {
     misc[0] = a.op != OP_SAMPLE && st->status != 0;
     misc[1] = 0;
     int o = 0;
@@ -115,14 +115,14 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   // the CDFs of all modes, back to back in mode order
 #pragma unroll
   for (int j = 0; j < kCdfRegs; ++j) {
-    const int e = tid + j * kBlock;
+    const int e = tid + j * kGatherThreads;
     if (e < sumdims) S.cdf()[e] = cv[j];
   }
-  for (int e = tid + kCdfRegs * kBlock; e < sumdims; e += kBlock) S.cdf()[e] = cdf_at(e);
+  for (int e = tid + kCdfRegs * kGatherThreads; e < sumdims; e += kGatherThreads) S.cdf()[e] = cdf_at(e);
   __syncthreads();
   if (misc[0]) return;
   const int n = uniform_int(misc[3]);
-  for (int e = tid; e < nm1 * nf; e += kBlock) {
+  for (int e = tid; e < nm1 * nf; e += kGatherThreads) {
     const int sl = e / nf, f = e - sl * nf;
     const int k = sl < n ? sl : sl + 1;
     const double* Ck = S.cdf() + S.coff()[k];
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   // ---- per fibre: p_f, w_f, the fibre's byte offset in copy n -------------
   const int ldn = dp->ld[n];
   const int64_t esz = BF16 ? 2 : 4;
-  for (int f = tid; f < S.bpad; f += kBlock) {
+  for (int f = tid; f < S.bpad; f += kGatherThreads) {
     const int ro = (f >> 4) * 16 + (f & 3) * 4 + ((f >> 2) & 3);
     if (f < nf) {
       double p = 1.0;
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   float* wht = S.wht();
   {
     constexpr int CPI = 4, ipf = 16 * RT / CPI;
-    for (int itm = tid; itm < S.bpad * ipf; itm += kBlock) {
+    for (int itm = tid; itm < S.bpad * ipf; itm += kGatherThreads) {
       const int f = itm / ipf, c0 = (itm - f * ipf) * CPI;
       float h[CPI];
 #pragma unroll
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   // same for all blocks; waves of a short last block may get no chunk.
   const int nck_full = FB / (4 * U);
   const int kp = wide_kparts(nst, nck_full);
-  const int tgn = kWaves / kp;
+  const int tgn = kGatherWaves / kp;
   const int tg = wave % tgn, kpart = wave / tgn;
   const int c0 = kpart * nck_full / kp;
   const int c1 = min((kpart + 1) * nck_full / kp, nck);
@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(kBlock) wide_gather_kernel(const ChainDesc* __
   __syncthreads();
   // the first chunk's fibre loads are in flight while this slice's Gs forms
   if (total > 0) load(xa, pa, 0);
-  compute_gs<RT>(S);
+  compute_gs<RT, kGatherThreads>(S);
   for (int c = 0; c < total; c += 2) {
     if (c + 1 < total) load(xb, pb, c + 1);
     compute(xa, pa, c);
@@ -547,7 +547,7 @@ static hipError_t gather_rt(const ChainDesc* d, int nblocks, size_t lds, const W
                             hipStream_t s) {
   hipError_t e = gather_attr<RT, BF16>();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((wide_gather_kernel<RT, BF16>), dim3(nblocks), dim3(kBlock), lds, s, d, a);
+  hipLaunchKernelGGL((wide_gather_kernel<RT, BF16>), dim3(nblocks), dim3(kGatherThreads), lds, s, d, a);
   return hipGetLastError();
 }
 
