@@ -196,6 +196,7 @@ def main():
         extra["time_to_fit"] = time_to_fit(make, target=0.99, every=25, max_steps=40000)
     if not args.no_batch:
         extra["batch"] = batch_bench(args.batch_count, seq=not args.no_seq)
+    extra["small_workload"] = small_workload()
     if not args.no_grid:
         extra["grid_sweep"] = grid_sweep(w, X32, args)
     if not args.no_variance:
@@ -426,6 +427,39 @@ def variance_study(steps=1000, every=100, B=18):
         out[f"data_{'ii' if which == 2 else 'iii'}"] = rows
         out[f"data_{'ii' if which == 2 else 'iii'}_eval_seconds"] = el
         out[f"data_{'ii' if which == 2 else 'iii'}_eval_gbps"] = nbytes / el / 1e9
+        dec.close()
+    return out
+
+
+def small_workload(steps=2000):
+    """The 30x30x30 workload (R 5, B 18, SNR 40 dB, FP32 storage): its 2000
+    steps in one persistent launch per importance sampler, with the fit
+    after them."""
+    import numpy as np
+    import torch
+
+    import cpd_inputs as ci
+    import paper_2103_04081_amd as P
+    w = ci.workload(1)
+    out = {"workload": "30x30x30 tensor, R=5 (true rank 5), B=18, SNR 40 dB, FP32 storage, "
+                       f"AdaGrad eta=1.0, {steps} steps"}
+    for sampler in ("euclidean", "leverage"):
+        dec = P.Decomposition(np.asfortranarray(w["X"].astype(np.float32)), w["A0"], B=w["B"],
+                              sampler=sampler, rule="adagrad", eta=1.0, storage="f32",
+                              seed=w["seed"])
+        dec.step(50)
+        dec.sync()
+        t0 = dec.t
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(dec.stream)
+        dec.step(steps)
+        ev1.record(dec.stream)
+        ev1.synchronize()
+        dec.sync()
+        ms = ev0.elapsed_time(ev1)
+        out[sampler] = {"steps_per_s": steps / (ms / 1e3), "us_per_step": ms * 1e3 / steps,
+                        "fit_after": dec.fit(), "t": dec.t - t0}
         dec.close()
     return out
 

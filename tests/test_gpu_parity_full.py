@@ -89,3 +89,33 @@ def test_scene_shaped_stand_ins(dims, R, sampler):
                            dtype=np.float32)
     _replay(prob, 20, 15, sampler=sampler, storage="f32", eta=1.0, seed=1300,
             label=f"{dims} R{R} B20 {sampler}")
+
+
+@pytest.mark.parametrize("sampler", ["euclidean", "leverage"])
+def test_small_workload_2000_steps(sampler):
+    """The 30x30x30 workload (R 5, B 18, SNR 40 dB) for its 2000 steps: the
+    first 100 replayed against the oracle (iterates within 1e-5); over the
+    whole run the device and the oracle draw on their own (FP32 and FP64
+    iterates put some draws on different sides of a CDF boundary, so only
+    the outcome is compared): both reach a fit within 1e-3 of each other,
+    above 0.999, and recover the true factors (match score > 0.99)."""
+    from helpers import factor_match_score
+    w = ci.workload(1)
+    print("CASE small workload", sampler, flush=True)
+    _replay(w, w["B"], 100, sampler=sampler, storage="f32", eta=1.0, seed=w["seed"],
+            label=f"30^3 R5 B18 {sampler}")
+    dec = gpu_decomposition(w, w["B"], sampler=sampler, eta=1.0, seed=w["seed"])
+    orc = O.Oracle(w["X"], w["A0"], B=w["B"], sampler=sampler, eta=1.0, seed=w["seed"])
+    dec.step(2000)
+    for _ in range(2000):
+        orc.step()
+    f_gpu, f_ora = dec.fit(), orc.fit()
+    A = [a.astype(np.float64) for a in dec.factors()]
+    fms_gpu = factor_match_score(A, w["A_true"])
+    fms_ora = factor_match_score(orc.A, w["A_true"])
+    print(f"2000 steps: fit {f_gpu:.6f} (oracle {f_ora:.6f}), factor match {fms_gpu:.4f} "
+          f"(oracle {fms_ora:.4f})", flush=True)
+    assert abs(f_gpu - f_ora) <= 1e-3
+    assert f_gpu > 0.999 and f_ora > 0.999
+    assert fms_gpu > 0.99 and fms_ora > 0.99
+    dec.close()
