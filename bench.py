@@ -197,6 +197,7 @@ def main():
     if not args.no_batch:
         extra["batch"] = batch_bench(args.batch_count, seq=not args.no_seq)
     extra["small_workload"] = small_workload()
+    extra["four_way"] = four_way()
     if not args.no_grid:
         extra["grid_sweep"] = grid_sweep(w, X32, args)
     if not args.no_variance:
@@ -428,6 +429,41 @@ def variance_study(steps=1000, every=100, B=18):
         out[f"data_{'ii' if which == 2 else 'iii'}_eval_seconds"] = el
         out[f"data_{'ii' if which == 2 else 'iii'}_eval_gbps"] = nbytes / el / 1e9
         dec.close()
+    return out
+
+
+def four_way(steps=2000):
+    """The 4-way workload: 120^4 (207M entries), R = 20, B = 512, SNR 30 dB
+    (tensor built on the device), FP32 vs BF16 storage, persistent step,
+    Euclidean sampler, AdaGrad eta = 1.5; steps/s and algorithmic GB/s."""
+    import torch
+
+    import cpd_inputs as ci
+    import paper_2103_04081_amd as P
+    spec = {"dims": (120, 120, 120, 120), "R": 20, "data_seed": 1003, "init_seed": 2003,
+            "snr_db": 30.0}
+    X, A0 = ci.device_problem(spec, "cuda")
+    out = {"workload": "120x120x120x120 tensor, R=20, B=512, N(0,1) factors, SNR 30 dB; "
+                       "Euclidean sampler, AdaGrad eta=1.5; persistent step"}
+    for storage, elem in (("f32", 4), ("bf16", 2)):
+        dec = P.Decomposition(X, A0, B=512, sampler="euclidean", rule="adagrad", eta=1.5,
+                              storage=storage, seed=3003)
+        dec.step(200)
+        dec.sync()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(dec.stream)
+        dec.step(steps)
+        ev1.record(dec.stream)
+        ev1.synchronize()
+        dec.sync()
+        ms = ev0.elapsed_time(ev1) / steps
+        sb = step_bytes(list(spec["dims"]), spec["R"], 512, elem)
+        out[storage] = {"steps_per_s": 1e3 / ms, "us_per_step": ms * 1e3, "bytes_per_step": sb,
+                        "gbps": sb / ms / 1e6, "hbm_frac": sb / ms / 1e6 / 8000.0,
+                        "fit_after": dec.fit()}
+        dec.close()
+    del X
     return out
 
 

@@ -119,3 +119,37 @@ def test_small_workload_2000_steps(sampler):
     assert f_gpu > 0.999 and f_ora > 0.999
     assert fms_gpu > 0.99 and fms_ora > 0.99
     dec.close()
+
+
+def test_full_120_4way_storage_error_vs_fp64_oracle():
+    """The 120^4 workload (R 20, B 512) in FP32 and in BF16 storage, each
+    against the FP64 oracle run on the unrounded tensor with the device's
+    draws (fixed step below the stability bound, so iterates stay smooth
+    in the data): the error of each storage type vs the FP64 oracle."""
+    print("CASE 120^4 storage error", flush=True)
+    w32 = ci.workload(3)
+    lam = 0.0
+    for n in range(4):
+        V = np.ones((w32["R"], w32["R"]))
+        for k, A in enumerate(w32["A0"]):
+            if k != n:
+                V = V * (A.T @ A)
+        lam = max(lam, float(np.linalg.eigvalsh(V)[-1]))
+    alpha = 0.1 / lam
+    errs = {}
+    for storage in ("f32", "bf16"):
+        dec = gpu_decomposition(w32, w32["B"], sampler="euclidean", storage=storage, rule="fixed",
+                                alpha=alpha, seed=w32["seed"])
+        orc64 = O.Oracle(w32["X64"], w32["A0"], B=w32["B"], sampler="euclidean", rule="fixed",
+                         alpha=alpha, seed=w32["seed"])
+        for t in range(12):
+            n, idx, _ = dec.sample(t)
+            orc64.step(replay=(n, idx))
+            dec.step(1)
+        A = dec.factors()
+        errs[storage] = max(rel(A[k], orc64.A[k]) for k in range(4))
+        dec.close()
+    print(f"120^4 R20 B512, 12 steps, fixed step: error vs FP64 oracle on the unrounded tensor: "
+          f"FP32 storage {errs['f32']:.3e}, BF16 storage {errs['bf16']:.3e}", flush=True)
+    assert errs["f32"] <= 1e-5
+    assert errs["bf16"] <= 2e-2
