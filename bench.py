@@ -95,6 +95,8 @@ def parse():
     ap.add_argument("--grid-b", default="4096,16384,65536,131072,262144",
                     help="mini-batch sizes of the grid sweep")
     ap.add_argument("--grid-steps", type=int, default=100)
+    ap.add_argument("--no-oracle-extra", action="store_true",
+                    help="skip the oracle timings of the small, 4-way and batch workloads")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MiB (a "
                          "known-size kernel to scale hardware byte counters)")
@@ -113,6 +115,80 @@ def calib_copy(mb):
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
+
+
+def _oracle_batch_member(spec, budget):
+    """One member of the 64-tensor recipe solved by the FP64 oracle (in a
+    worker process): AdaGrad steps with the explicit-reconstruction fit every
+    25 steps, until fit 0.99, 5000 steps or the time budget."""
+    import cpd_inputs as ci
+    import oracle as O
+    t0 = time.perf_counter()
+    prob = ci.make_problem(spec["dims"], spec["R"], data_seed=spec["data_seed"],
+                           init_seed=spec["init_seed"], snr_db=spec["snr_db"], dtype="bf16")
+    orc = O.Oracle(prob["X"], prob["A0"], B=spec["B"], sampler="euclidean", rule="adagrad",
+                   eta=BATCH_ETA, seed=spec["seed"], stream_id=spec["stream_id"])
+    t1 = time.perf_counter()
+    steps, fit = 0, -1.0
+    while steps < 5000 and time.perf_counter() - t0 < budget:
+        for _ in range(25):
+            orc.step()
+        steps += 25
+        fit = orc.fit()
+        if fit >= 0.99:
+            break
+    return {"steps": steps, "fit": fit, "reached": fit >= 0.99,
+            "solve_seconds": time.perf_counter() - t1}
+
+
+def oracle_beside(budget=25.0):
+    """The FP64 oracle beside the other workloads, on bounded samples: the
+    small 30^3 workload (its 2000 steps, one core), the 120^4 workload (a
+    few steps, one core) and the 64-tensor batch recipe (its first members,
+    one per worker process, each to fit 0.99 within the time budget)."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+
+    import cpd_inputs as ci
+    import oracle as O
+    out = {}
+    w1 = ci.workload(1)
+    orc = O.Oracle(w1["X"], w1["A0"], B=w1["B"], sampler="euclidean", rule="adagrad", eta=1.0,
+                   seed=w1["seed"])
+    t0 = time.perf_counter()
+    for _ in range(2000):
+        orc.step()
+    el = time.perf_counter() - t0
+    out["small_workload"] = {"value": 2000 / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                             "sample": "all 2000 steps of the 30^3 workload (Euclidean)",
+                             "fit_after": orc.fit()}
+    w3 = ci.workload(3)
+    orc = O.Oracle(w3["X"], w3["A0"], B=w3["B"], sampler="euclidean", rule="adagrad", eta=1.5,
+                   seed=w3["seed"])
+    t0 = time.perf_counter()
+    n = 0
+    while n < 200 and time.perf_counter() - t0 < 10.0:
+        orc.step()
+        n += 1
+    el = time.perf_counter() - t0
+    out["four_way"] = {"value": n / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                       "sample": f"first {n} steps of the 120^4 R20 B512 workload (FP32 data)"}
+    del orc, w3
+    workers = max(1, min(16, os.cpu_count() or 1))
+    specs = ci.batch_workload(count=64)[:workers]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers,
+                             mp_context=multiprocessing.get_context("spawn")) as ex:
+        res = list(ex.map(_oracle_batch_member, specs, [budget] * len(specs)))
+    wall = time.perf_counter() - t0
+    reached = sum(r["reached"] for r in res)
+    out["batch"] = {"value": reached / wall, "unit": "solves/s", "cores": workers,
+                    "kind": "oracle",
+                    "sample": f"first {len(specs)} members of the 64-tensor recipe, one per process, "
+                              f"each to fit 0.99 (explicit fit every 25 steps) within {budget:.0f} s",
+                    "reached": reached, "wall_seconds": wall,
+                    "steps": [r["steps"] for r in res]}
+    return out
 
 
 def cpu_baseline(w, seconds):
@@ -235,6 +311,8 @@ def main():
     out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        if not args.no_oracle_extra:
+            out["oracle_beside"] = oracle_beside()
     print(json.dumps(out), flush=True)
 
 

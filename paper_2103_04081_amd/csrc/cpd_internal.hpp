@@ -21,6 +21,7 @@ constexpr size_t kAlign = 256;
 constexpr int kLdAlign = 64;            // copy rows padded to 64 elements
 constexpr int kChunkSteps = 32;         // MFMA K-steps (4 fibres each) per chunk, for VW = RT = 1
 constexpr int kFibrePad = 4 * kChunkSteps;  // sampled fibres padded (zero weight) to full chunks
+constexpr int kFibreBufs = 2;           // register buffers of fibre chunks in the contraction
 constexpr double kRankTol = 1e-12;      // Cholesky pivot^2 <= tol * diagonal => rank deficient
 constexpr size_t kLdsBudget = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr int kFitRowsMin = 256;        // rows of copy 0 per fit block, at least

@@ -205,7 +205,7 @@ __device__ __forceinline__ bool contract_update(const ChainDesc* dp, const Smem&
   // c is multiplied.  Two accumulator sets (even / odd K-steps) halve the
   // dependent-accumulation chain.
   f4 acc2[RT][VW];
-  float xa[U][VW], xb[U][VW];
+  float xbuf[kFibreBufs][U][VW];
   auto load = [&](float (&x)[U][VW], int c) {
     const int it = c / nck;
     const int st = st_first + it * kWaves;
@@ -290,12 +290,18 @@ __device__ __forceinline__ bool contract_update(const ChainDesc* dp, const Smem&
   };
   const int total = nitems * nck;
   if (total > 0) {
-    load(xa, 0);
-    for (int c = 0; c < total; c += 2) {
-      if (c + 1 < total) load(xb, c + 1);
-      compute(xa, c);
-      if (c + 2 < total) load(xa, c + 2);
-      if (c + 1 < total) compute(xb, c + 1);
+    // kFibreBufs register buffers: the loads of the next kFibreBufs - 1
+    // chunks are in flight while a chunk is multiplied
+#pragma unroll
+    for (int j = 0; j < kFibreBufs - 1; ++j)
+      if (j < total) load(xbuf[j], j);
+    for (int c = 0; c < total; c += kFibreBufs) {
+#pragma unroll
+      for (int j = 0; j < kFibreBufs; ++j) {
+        if (c + j + kFibreBufs - 1 < total)
+          load(xbuf[(j + kFibreBufs - 1) % kFibreBufs], c + j + kFibreBufs - 1);
+        if (c + j < total) compute(xbuf[j], c + j);
+      }
     }
   }
   if (ks > 1) {

@@ -14,6 +14,7 @@ namespace cpdmi {
 constexpr int kWideFibresMax = 512;
 constexpr int kGatherThreads = 512;  // threads of a gather block
 constexpr int kGatherWaves = kGatherThreads / 64;
+constexpr int kGatherBufs = 2;  // register buffers of fibre chunks per wave
 
 // Fibres per block of the gather kernel for mini-batch B: about 256 blocks
 // while the slices stay within [128, 512] fibres (measured on 300-element

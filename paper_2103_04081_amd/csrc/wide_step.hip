@@ -255,8 +255,8 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
   f4 acc[RT][VW], acc2[RT][VW];
   // two register buffers of fibre values, each with the A^(n) entries of the
   // -Gs A^(n)T term, loaded with the last chunk of a tile
-  float xa[U][VW], xb[U][VW];
-  float pa[4 * RT][VW], pb[4 * RT][VW];
+  float xbuf[kGatherBufs][U][VW];
+  float pbuf[kGatherBufs][4 * RT][VW];
   auto load = [&](float (&x)[U][VW], float (&pA)[4 * RT][VW], int c) {
     const int it = c / nckw;
     const int stl = tg + it * tgn;
@@ -375,14 +375,20 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
     }
   }
   __syncthreads();
-  // the first chunk's fibre loads are in flight while this slice's Gs forms
-  if (total > 0) load(xa, pa, 0);
+  // the first chunks' fibre loads are in flight while this slice's Gs forms;
+  // then the loads of the next kGatherBufs - 1 chunks while one is multiplied
+#pragma unroll
+  for (int j = 0; j < kGatherBufs - 1; ++j)
+    if (j < total) load(xbuf[j], pbuf[j], j);
   compute_gs<RT, kGatherThreads>(S);
-  for (int c = 0; c < total; c += 2) {
-    if (c + 1 < total) load(xb, pb, c + 1);
-    compute(xa, pa, c);
-    if (c + 2 < total) load(xa, pa, c + 2);
-    if (c + 1 < total) compute(xb, pb, c + 1);
+  for (int c = 0; c < total; c += kGatherBufs) {
+#pragma unroll
+    for (int j = 0; j < kGatherBufs; ++j) {
+      constexpr int kNb = kGatherBufs;
+      if (c + j + kNb - 1 < total)
+        load(xbuf[(j + kNb - 1) % kNb], pbuf[(j + kNb - 1) % kNb], c + j + kNb - 1);
+      if (c + j < total) compute(xbuf[j], pbuf[j], c + j);
+    }
   }
 }
 
