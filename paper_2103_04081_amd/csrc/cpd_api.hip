@@ -124,12 +124,18 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
   off = align_up(off + sizeof(int32_t) * fit_table_len(1));
   w->wide_info = w->wide_part = 0;
   if (w->grid) {
-    int imax = 0;
-    for (int k = 0; k < p->N; ++k) imax = std::max(imax, p->dims[k]);
     w->wide_info = off;
     off = align_up(off + sizeof(WideInfo));
     w->wide_part = off;
-    off = align_up(off + sizeof(float) * (size_t)w->wide_blocks * kWideMaxParts * p->R * imax);
+    // parts per block and mode as the gather kernel splits them
+    const int vw = o->storage == CPD_BF16 ? 2 : 1;
+    const int nck = w->wide_fb / (4 * chunk_steps(vw, (p->R + 15) / 16));
+    size_t per_block = 0;
+    for (int k = 0; k < p->N; ++k) {
+      const int nst = (p->dims[k] + 16 * vw - 1) / (16 * vw);
+      per_block = std::max(per_block, (size_t)wide_kparts(nst, nck) * p->R * p->dims[k]);
+    }
+    off = align_up(off + sizeof(float) * (size_t)w->wide_blocks * per_block);
   }
   for (int k = 0; k < p->N; ++k) {
     const size_t fb = sizeof(float) * (size_t)p->dims[k] * p->R;

@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "../../include/cpd.h"
 
 namespace cpdmi {
@@ -147,6 +149,19 @@ __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + 
 template <typename T>
 __device__ __forceinline__ CPD_GLOBAL T* gmem(T* p) {
   return (CPD_GLOBAL T*)(p);
+}
+
+// Raises a kernel's dynamic-LDS limit once per device (bit d of *done set
+// for device d; concurrent first calls may both set it, which is harmless).
+inline hipError_t set_lds_limit_once(const void* fn, int bytes, std::atomic<uint32_t>* done) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint32_t bit = 1u << (dev & 31);
+  if (done->load(std::memory_order_acquire) & bit) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) done->fetch_or(bit, std::memory_order_acq_rel);
+  return e;
 }
 
 // Round an FP32 value to bfloat16, ties to even (NaN kept quiet).

@@ -579,16 +579,13 @@ FitPlan plan_fit(const ChainDesc* descs, int nchains, int32_t* tables) {
 
 hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_tables, int nchains,
                       const FitPlan& fp, int dtype, bool inner, hipStream_t stream) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)fit_partial_kernel<float, true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kFitLdsMax);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)fit_partial_kernel<uint16_t, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kFitLdsMax);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint32_t> attr_f32{0}, attr_bf16{0};
+  hipError_t ea = set_lds_limit_once((const void*)fit_partial_kernel<float, true>,
+                                     (int)kFitLdsMax, &attr_f32);
+  if (ea != hipSuccess) return ea;
+  ea = set_lds_limit_once((const void*)fit_partial_kernel<uint16_t, true>, (int)kFitLdsMax,
+                          &attr_bf16);
+  if (ea != hipSuccess) return ea;
   for (int g = 0; g < 2; ++g) {
     if (fp.blocks[g] == 0) continue;
     const int32_t* tab = d_tables + (g + 1) * (nchains + 1);

@@ -656,13 +656,9 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
 template <int RT>
 static hipError_t launch_rt(const ChainDesc* descs, int nchains, size_t lds_bytes,
                             const StepArgs& args, hipStream_t stream) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)chain_kernel<RT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static std::atomic<uint32_t> attr_set{0};
+  hipError_t e = set_lds_limit_once((const void*)chain_kernel<RT>, 160 * 1024, &attr_set);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(chain_kernel<RT>, dim3(nchains), dim3(kBlock), lds_bytes, stream, descs, args);
   return hipGetLastError();
 }

@@ -511,26 +511,14 @@ __global__ void __launch_bounds__(kBlock) wide_refresh_kernel(const ChainDesc* _
 
 template <int RT, bool BF16>
 static hipError_t gather_attr() {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)wide_gather_kernel<RT, BF16>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  return hipSuccess;
+  static std::atomic<uint32_t> attr_set{0};
+  return set_lds_limit_once((const void*)wide_gather_kernel<RT, BF16>, 160 * 1024, &attr_set);
 }
 
 template <int RT>
 static hipError_t refresh_attr() {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)wide_refresh_kernel<RT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  return hipSuccess;
+  static std::atomic<uint32_t> attr_set{0};
+  return set_lds_limit_once((const void*)wide_refresh_kernel<RT>, 160 * 1024, &attr_set);
 }
 
 template <int RT>
