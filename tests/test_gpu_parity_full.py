@@ -153,3 +153,15 @@ def test_full_120_4way_storage_error_vs_fp64_oracle():
           f"FP32 storage {errs['f32']:.3e}, BF16 storage {errs['bf16']:.3e}", flush=True)
     assert errs["f32"] <= 1e-5
     assert errs["bf16"] <= 2e-2
+
+
+@pytest.mark.parametrize("which,B,storage", [(2, 65536, "f32"), (3, 65536, "bf16")])
+def test_full_size_grid_step(which, B, storage):
+    """The grid step at full tensor sizes and a batch the bench sweeps
+    (300^3 FP32 and 120^4 BF16 with B = 65536, 256 gather blocks): draws bit
+    for bit against the oracle's sampler on the device's CDFs, then three
+    steps replayed against the oracle."""
+    w = ci.workload(which, dtype=storage if storage == "bf16" else None)
+    print("CASE full-size grid", which, B, storage, flush=True)
+    _replay(w, B, 3, sampler="euclidean", storage=storage, eta=1.0, seed=w["seed"],
+            label=f"{w['name']} grid B={B} {storage}")
