@@ -478,7 +478,8 @@ def serve_bench(n_requests=200, rate=50.0, saturate=False):
 def variance_study(steps=1000, every=100, B=18):
     """The variance of the sampled gradient (mode 1, variance theorem) for the
     three samplers along an EAdawsCPD run on the paper's Data II and Data III,
-    and the time of one evaluation (two passes over copy 1)."""
+    and the wall time of one evaluation (scratch allocation, the sampler's
+    CDFs and one pass over copy 1)."""
     import numpy as np
     import torch
 
@@ -502,7 +503,7 @@ def variance_study(steps=1000, every=100, B=18):
         for _ in range(5):
             dec.variance(0, "euclidean")
         el = (time.perf_counter() - t0) / 5
-        nbytes = 2 * 300 * 320 * 300 * 4  # two passes over copy 1 (rows padded to 320)
+        nbytes = 300 * 320 * 300 * 4  # one pass over copy 1 (rows padded to 320)
         out[f"data_{'ii' if which == 2 else 'iii'}"] = rows
         out[f"data_{'ii' if which == 2 else 'iii'}_eval_seconds"] = el
         out[f"data_{'ii' if which == 2 else 'iii'}_eval_gbps"] = nbytes / el / 1e9

@@ -8,18 +8,23 @@
 // per-mode q/Q of the integer CDFs), and grad f = A^(n) (hadamard_{k!=n}
 // A^(k)T A^(k)) - X_(n) Z^(n).
 //
-// Three kernels over copy n (row j = fibre j):
-//   variance_mttkrp_kernel  partial sums of M = X_(n) Z^(n): one wave per
-//                           (16-column tile of I_n, range of rows), M^T
-//                           tiles on the matrix cores (Z^T as the A operand,
-//                           the fibres as the B operand);
-//   variance_terms_kernel   per 16-row tile: A^(n) z_j for 16 columns at a
-//                           time on the matrix cores (Z tile as the A
-//                           operand, A^(n)^T as the B operand), minus x_j,
-//                           squared and summed per row; then
-//                           ||r_j||^2 ||z_j||^2 / p_j summed in FP64;
-//   variance_final_kernel   sum of the partials in a fixed order, the Gram
-//                           Hadamard product, grad f and the variance (FP64).
+// One pass over copy n (row j = fibre j) and three small kernels:
+//   variance_pass_kernel<RT>  blocks of 16-row tiles of a row range and a
+//                             group of 16-column tiles: the KRP rows z_j of
+//                             the tile (LDS), then per column tile on the
+//                             matrix cores both A^(n) z_j (Z tile as the A
+//                             operand, A^(n) rows from LDS as the B operand)
+//                             minus x_j, squared and summed per row, and the
+//                             block's part of M = X_(n) Z^(n) (Z^T as the A
+//                             operand, the same fibre values as the B
+//                             operand); per-row sums of squares per column
+//                             group and ||z_j||^2 / p_j go to scratch;
+//   variance_msum_kernel      M: the block parts summed in a fixed order
+//                             (FP64);
+//   variance_terms_kernel     sum_j ||r_j||^2 ||z_j||^2 / p_j per block of
+//                             rows (FP64);
+//   variance_final_kernel     the terms summed in a fixed order, the Gram
+//                             Hadamard product, grad f and the variance.
 #include <cstring>
 #include <string>
 
@@ -29,188 +34,239 @@ namespace cpdmi {
 
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
-namespace {
 
-constexpr int kVarWaveRows = 16;
+constexpr int kVpThreads = 256;  // threads of a pass block (four waves)
 
-// Element e of copy n (row j, column i) as FP32.
-__device__ __forceinline__ float load_x(const ChainDesc* dp, int n, int64_t j, int i) {
-  const int64_t off = j * dp->ld[n] + i;
-  if (dp->dtype == CPD_BF16) {
-    const uint16_t v = gmem((const uint16_t*)dp->X[n])[off];
-    return __uint_as_float((uint32_t)v << 16);
-  }
-  return gmem((const float*)dp->X[n])[off];
+// Column tiles of one wave held in registers for a rank-tile count RT.
+__host__ __device__ constexpr int var_tiles_per_wave(int rt) { return rt >= 4 ? 2 : 8 / rt; }
+
+// LDS of a pass block: A^(n) rows of the group's columns (ranks padded to
+// 16 RT), the Z tile (16 rows, stride 16 RT + 1), row multi-indices, the
+// per-wave row sums.
+__host__ __device__ inline size_t var_pass_lds(int tpg, int RT) {
+  return sizeof(float) * (size_t)tpg * 16 * 16 * RT + sizeof(float) * 16 * (16 * RT + 1) +
+         sizeof(int32_t) * 16 * kMaxModes + sizeof(double) * 4 * 16;
 }
 
-// Multi-index of row j of copy n over the modes k != n (ascending, the
-// lowest fastest): writes i_k into ik[k].
-__device__ __forceinline__ void row_index(const ChainDesc* dp, int n, int64_t j, int* ik) {
-  int64_t rem = j;
-  for (int k = 0; k < dp->N; ++k) {
-    if (k == n) continue;
-    const int Ik = dp->dims[k];
-    const int64_t nx = rem / Ik;
-    ik[k] = (int)(rem - nx * Ik);
-    rem = nx;
-  }
-}
-
-// z_j(r) = prod_{k != n} A^(k)(i_k, r) (ascending k); 0 for r >= R.
-__device__ __forceinline__ float z_entry(const ChainDesc* dp, int n, const int* ik, int r) {
-  if (r >= dp->R) return 0.f;
-  float z = 1.f;
-  bool first = true;
-  for (int k = 0; k < dp->N; ++k) {
-    if (k == n) continue;
-    const float a = gmem((const float*)dp->A[k])[(int64_t)ik[k] * dp->R + r];
-    z = first ? a : z * a;
-    first = false;
-  }
-  return z;
-}
-
-}  // namespace
-
-// One wave per block.  Block (t, c): column tile t (16 columns of I_n),
-// rows [c * rpc, (c + 1) * rpc).  partial[c][i][r] = sum over its rows of
-// x_j(i) z_j(r).
-__global__ void __launch_bounds__(64) variance_mttkrp_kernel(const ChainDesc* __restrict__ dp,
-                                                             int n, int nchunks,
-                                                             float* __restrict__ partial) {
-  const int In = dp->dims[n], R = dp->R, RT = (R + 15) / 16;
+// Block (c, g): rows [c rpc, (c + 1) rpc) in 16-row tiles, column tiles
+// [g tpg, (g + 1) tpg); wave w takes column tiles g tpg + w, + 4, ...
+//   rr[g][j]      sum over the group's columns of (A^(n) z_j - x_j)^2 (FP64)
+//   zw[j]         ||z_j||^2 / p_j (group 0)
+//   part[c][i][r] sum over the block's rows of x_j(i) z_j(r)
+template <int RT>
+__global__ void __launch_bounds__(kVpThreads) variance_pass_kernel(
+    const ChainDesc* __restrict__ dp, int n, int64_t rpc, int tpg, float* __restrict__ part,
+    double* __restrict__ rr, double* __restrict__ zw) {
+  extern __shared__ __align__(16) unsigned char vsm[];
+  constexpr int Rp = 16 * RT, ZS = Rp + 1, MT = var_tiles_per_wave(RT);
+  const int In = dp->dims[n], R = dp->R, N = dp->N;
   int64_t J = 1;
-  for (int k = 0; k < dp->N; ++k)
+  for (int k = 0; k < N; ++k)
     if (k != n) J *= dp->dims[k];
-  const int ntiles = (In + 15) / 16;
-  const int tile = blockIdx.x % ntiles, c = blockIdx.x / ntiles;
-  const int64_t rpc = (J + nchunks - 1) / nchunks;
-  const int64_t j0 = (int64_t)c * rpc, j1 = j0 + rpc < J ? j0 + rpc : J;
-  const int lane = threadIdx.x, kg = lane >> 4, rq = lane & 15;
-  const int i = tile * 16 + rq;
-  vf4 acc[4];
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt) acc[rt] = vf4{0.f, 0.f, 0.f, 0.f};
-  int ik[kMaxModes];
-  for (int64_t jb = j0; jb < j1; jb += 4) {
-    const int64_t j = jb + kg;
-    const bool ok = j < j1;
-    float x = 0.f;
-    float zr[4] = {0.f, 0.f, 0.f, 0.f};
-    if (ok) {
-      if (i < In) x = load_x(dp, n, j, i);
-      row_index(dp, n, j, ik);
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-        if (rt < RT) zr[rt] = z_entry(dp, n, ik, 16 * rt + rq);
-    }
-    // A operand: Z^T[rank 16 rt + rq][row slot kg]; B operand: X[row slot kg][column rq]
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-      if (rt < RT) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(zr[rt], x, acc[rt], 0, 0, 0);
-  }
-  // acc[rt][q] = M^T(rank 16 rt + 4 kg + q, column rq of the tile)
-  float* out = partial + (int64_t)c * In * R;
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
-    if (rt < RT)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 16 * rt + 4 * kg + q;
-        if (r < R && i < In) out[(int64_t)i * R + r] = acc[rt][q];
-      }
-}
-
-// One wave per block, rows [b * rpb, (b + 1) * rpb) in 16-row tiles.
-// terms[b] = sum over its rows of ||r_j||^2 ||z_j||^2 / p_j (FP64).
-__global__ void __launch_bounds__(64) variance_terms_kernel(const ChainDesc* __restrict__ dp,
-                                                            int n, int nblocks,
-                                                            double* __restrict__ terms) {
-  const int In = dp->dims[n], R = dp->R, RT = (R + 15) / 16;
-  int64_t J = 1;
-  for (int k = 0; k < dp->N; ++k)
-    if (k != n) J *= dp->dims[k];
-  const int64_t rpb = ((J + nblocks - 1) / nblocks + 15) / 16 * 16;
-  const int64_t r0 = (int64_t)blockIdx.x * rpb, r1 = r0 + rpb < J ? r0 + rpb : J;
-  const int lane = threadIdx.x, kg = lane >> 4, rq = lane & 15;
+  const int c = blockIdx.x, g = blockIdx.y;
+  const int nct = (In + 15) / 16;
+  const int ct0 = g * tpg, ct1 = ct0 + tpg < nct ? ct0 + tpg : nct;
+  const int64_t r0 = (int64_t)c * rpc, r1 = r0 + rpc < J ? r0 + rpc : J;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int gl = lane >> 4, cl = lane & 15;
+  float* As = (float*)vsm;                               // [tpg * 16][Rp]
+  float* Zt = As + (size_t)tpg * 16 * Rp;                // [16][ZS]
+  int32_t* ikl = (int32_t*)(Zt + 16 * ZS);               // [16][kMaxModes]
+  double* red = (double*)(vsm + var_pass_lds(tpg, RT) - sizeof(double) * 4 * 16);  // [4][16]
   const CPD_GLOBAL float* An = gmem((const float*)dp->A[n]);
-  double total = 0.0;
+  for (int e = tid; e < tpg * 16 * Rp; e += kVpThreads) {
+    const int i = ct0 * 16 + e / Rp, r = e % Rp;
+    As[e] = (i < In && r < R) ? An[(int64_t)i * R + r] : 0.f;
+  }
+  // row multi-index of row r0 + tid (threads 0..15), advanced by 16 per tile
   int ik[kMaxModes];
+  if (tid < 16) {
+    int64_t rem = r0 + tid;
+    for (int k = 0; k < N; ++k) {
+      ik[k] = 0;
+      if (k == n) continue;
+      const int64_t nx = rem / dp->dims[k];
+      ik[k] = (int)(rem - nx * dp->dims[k]);
+      rem = nx;
+    }
+  }
+  vf4 macc[MT][RT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) macc[m][rt] = vf4{0.f, 0.f, 0.f, 0.f};
+  const int64_t ld = dp->ld[n];
   for (int64_t t0 = r0; t0 < r1; t0 += 16) {
-    // this lane's A-operand row and its z entries at ranks 4 s + kg
-    const int64_t ja = t0 + rq;
-    const bool oka = ja < r1;
-    float za[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) za[s] = 0.f;
-    double zp = 0.0;  // ||z||^2 / p of row ja (complete after the reduction)
-    double p = 1.0;
-    if (oka) {
-      row_index(dp, n, ja, ik);
-#pragma unroll
-      for (int s = 0; s < 16; ++s)
-        if (s < 4 * RT) za[s] = z_entry(dp, n, ik, 4 * s + kg);
-      for (int k = 0; k < dp->N; ++k) {
+    if (tid < 16) {
+      for (int k = 0; k < N; ++k) ikl[tid * kMaxModes + k] = ik[k];
+      // next tile: row + 16 (odometer over the modes k != n, lowest fastest)
+      int carry = 16;
+      for (int k = 0; k < N && carry; ++k) {
+        if (k == n) continue;
+        const int v = ik[k] + carry;
+        carry = v / dp->dims[k];
+        ik[k] = v - carry * dp->dims[k];
+      }
+    }
+    __syncthreads();
+    // the KRP rows of the tile: z_j(r) = prod_{k != n} A^(k)(i_k, r), ascending k
+    for (int e = tid; e < 16 * Rp; e += kVpThreads) {
+      const int row = e / Rp, r = e - row * Rp;
+      float z = 0.f;
+      if (t0 + row < r1 && r < R) {
+        bool first = true;
+        for (int k = 0; k < N; ++k) {
+          if (k == n) continue;
+          const float a = gmem((const float*)dp->A[k])[(int64_t)ikl[row * kMaxModes + k] * R + r];
+          z = first ? a : z * a;
+          first = false;
+        }
+      }
+      Zt[row * ZS + r] = z;
+    }
+    __syncthreads();
+    if (g == 0 && tid < 16 && t0 + tid < r1) {
+      // p_j: product over k != n of q / Q of the sampler's integer CDFs
+      double p = 1.0;
+      for (int k = 0; k < N; ++k) {
         if (k == n) continue;
         const CPD_GLOBAL double* C = gmem((const double*)dp->C[k]);
+        const int i = ikl[tid * kMaxModes + k];
         const double Q = C[dp->dims[k] - 1];
-        const double lo = ik[k] ? C[ik[k] - 1] : 0.0;
-        p = p * ((C[ik[k]] - lo) / Q);
+        p = p * ((C[i] - (i ? C[i - 1] : 0.0)) / Q);
       }
+      float z2 = 0.f;
+      for (int r = 0; r < Rp; ++r) z2 = fmaf(Zt[tid * ZS + r], Zt[tid * ZS + r], z2);
+      zw[t0 + tid] = p > 0.0 ? (double)z2 / p : 0.0;
     }
-    float z2 = 0.f;
-#pragma unroll
-    for (int s = 0; s < 16; ++s) z2 = fmaf(za[s], za[s], z2);
-    double z2d = (double)z2;
-    z2d += __shfl_xor(z2d, 16);
-    z2d += __shfl_xor(z2d, 32);
-    zp = (oka && p > 0.0) ? z2d / p : 0.0;
-    // residual rows 4 kg + q of the tile, 16 columns at a time
     double r2[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i0 = 0; i0 < In; i0 += 16) {
-      const int i = i0 + rq;
-      vf4 acc = vf4{0.f, 0.f, 0.f, 0.f};
+    // all fibre values of the wave's column tiles first (one wait), then the
+    // matrix-core work tile by tile
+    float xs[MT][4];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        if (s < 4 * RT) {
-          const int r = 4 * s + kg;
-          const float b = (i < In && r < R) ? An[(int64_t)i * R + r] : 0.f;
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(za[s], b, acc, 0, 0, 0);
-        }
-      }
+    for (int m = 0; m < MT; ++m) {
+      const int ct = ct0 + wave + 4 * m;
+      const int i = ct * 16 + cl;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t j = t0 + 4 * kg + q;
-        if (j < r1 && i < In) {
-          const float d = acc[q] - load_x(dp, n, j, i);
-          r2[q] += (double)(d * d);
+        const int64_t j = t0 + 4 * gl + q;
+        float v = 0.f;
+        if (ct < ct1 && j < r1 && i < In) {
+          if (dp->dtype == CPD_BF16)
+            v = __uint_as_float((uint32_t)gmem((const uint16_t*)dp->X[n])[j * ld + i] << 16);
+          else
+            v = gmem((const float*)dp->X[n])[j * ld + i];
         }
+        xs[m][q] = v;
       }
     }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int ct = ct0 + wave + 4 * m;
+      if (ct >= ct1) break;
+      const int i = ct * 16 + cl;
+      const float* x = xs[m];
+      // A^(n) z_j for rows 4 gl + q, column i: K = rank
+      vf4 y = vf4{0.f, 0.f, 0.f, 0.f};
+      const float* Ar = As + (size_t)((ct - ct0) * 16 + cl) * Rp;
+#pragma unroll
+      for (int s = 0; s < 4 * RT; ++s)
+        y = __builtin_amdgcn_mfma_f32_16x16x4f32(Zt[cl * ZS + 4 * s + gl], Ar[4 * s + gl], y, 0,
+                                                 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float d = y[q] - x[q];
+        if (t0 + 4 * gl + q < r1 && i < In) r2[q] += (double)(d * d);
+      }
+      // M^T tile += Z^T X: K-step q holds rows 4 gl + q
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          macc[m][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Zt[(4 * gl + q) * ZS + rt * 16 + cl],
+                                                             x[q], macc[m][rt], 0, 0, 0);
+    }
+    // per-row sums over the columns: the 16 lanes of a group, then the waves
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
 #pragma unroll
       for (int o = 1; o < 16; o <<= 1) r2[q] += __shfl_xor(r2[q], o);
-      // z^2/p of row 4 kg + q sits in lane (kg' = 0, rq = 4 kg + q)
-      const double zpq = __shfl(zp, 4 * kg + q);
-      if (rq == 0 && t0 + 4 * kg + q < r1) total += r2[q] * zpq;
+      if (cl == 0) red[wave * 16 + 4 * gl + q] = r2[q];
     }
+    __syncthreads();
+    if (tid < 16 && t0 + tid < r1)
+      rr[(int64_t)g * J + t0 + tid] = red[tid] + red[16 + tid] + red[32 + tid] + red[48 + tid];
+    __syncthreads();
+  }
+  // the block's part of M: macc[m][rt][q] = M^T(rank 16 rt + 4 gl + q, column ct * 16 + cl)
+  float* out = part + (int64_t)c * In * R;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int ct = ct0 + wave + 4 * m;
+    if (ct >= ct1) break;
+    const int i = ct * 16 + cl;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * rt + 4 * gl + q;
+        if (r < R && i < In) out[(int64_t)i * R + r] = macc[m][rt][q];
+      }
+  }
+}
+
+// M(e) = sum over the parts, in a fixed order (FP64): 16 entries per block,
+// 64 lane groups of 16 lanes summing parts g, g + 64, ..., then the groups
+// in order.
+__global__ void __launch_bounds__(1024) variance_msum_kernel(const float* __restrict__ part,
+                                                             int nparts, int E,
+                                                             double* __restrict__ M) {
+  __shared__ double red[64][17];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = wave * 4 + (lane >> 4), ec = lane & 15;
+  const int e = blockIdx.x * 16 + ec;
+  double s = 0.0;
+  if (e < E)
+    for (int b = grp; b < nparts; b += 64) s += (double)gmem(part)[(int64_t)b * E + e];
+  red[grp][ec] = s;
+  __syncthreads();
+  if (threadIdx.x < 16 && blockIdx.x * 16 + (int)threadIdx.x < E) {
+    double m = 0.0;
+    for (int q = 0; q < 64; ++q) m += red[q][threadIdx.x];
+    M[blockIdx.x * 16 + threadIdx.x] = m;
+  }
+}
+
+// terms[b] = sum over rows [b rpb, (b + 1) rpb) of (sum_g rr[g][j]) zw[j].
+__global__ void __launch_bounds__(256) variance_terms_kernel(const double* __restrict__ rr,
+                                                             const double* __restrict__ zw,
+                                                             int64_t J, int ngroups,
+                                                             int64_t rpb,
+                                                             double* __restrict__ terms) {
+  __shared__ double red[4];
+  const int64_t j0 = (int64_t)blockIdx.x * rpb;
+  const int64_t j1 = j0 + rpb < J ? j0 + rpb : J;
+  double t = 0.0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+    double r = 0.0;
+    for (int g = 0; g < ngroups; ++g) r += rr[(int64_t)g * J + j];
+    t += r * zw[j];
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
-  if (lane == 0) terms[blockIdx.x] = total;
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) terms[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // out[0] = variance, out[1] = (1/B) sum of the terms, out[2] = ||grad f||^2 / B.
 __global__ void __launch_bounds__(1024) variance_final_kernel(const ChainDesc* __restrict__ dp,
-                                                              int n, int nchunks,
-                                                              const float* __restrict__ partial,
+                                                              int n, const double* __restrict__ M,
                                                               int nblocks,
                                                               const double* __restrict__ terms,
                                                               double* __restrict__ out) {
   __shared__ double red[16];
   __shared__ double had[kMaxRank * kMaxRank];
-  __shared__ float rows[64 * kMaxRank];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = dp->R, R2 = R * R, In = dp->dims[n];
   double t = 0.0;
@@ -222,40 +278,55 @@ __global__ void __launch_bounds__(1024) variance_final_kernel(const ChainDesc* _
   double T = 0.0;
   for (int w = 0; w < 16; ++w) T += red[w];
   __syncthreads();
-  // H = hadamard_{k != n} A^(k)T A^(k), FP64, rows staged through LDS
+  // H = hadamard_{k != n} A^(k)T A^(k), FP64: every thread takes one (pair,
+  // row range) item; the row ranges of a pair are summed in a fixed order
+  // items: npairs * nrg <= max(npairs, blockDim.x) <= kMaxRank (kMaxRank + 1) / 2
+  __shared__ double gpart[kMaxRank * (kMaxRank + 1) / 2];
   for (int p = tid; p < R2; p += blockDim.x) had[p] = 1.0;
+  const int npairs = R * (R + 1) / 2;
   for (int k = 0; k < dp->N; ++k) {
     if (k == n) continue;
     const CPD_GLOBAL float* A = gmem((const float*)dp->A[k]);
     const int Ik = dp->dims[k];
-    double g[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i0 = 0; i0 < Ik; i0 += 64) {
-      const int nr = Ik - i0 < 64 ? Ik - i0 : 64;
-      __syncthreads();
-      for (int e = tid; e < nr * R; e += blockDim.x) rows[e] = A[(int64_t)i0 * R + e];
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int p = tid + q * 1024;
-        if (p < R2) {
-          const int r = p / R, c = p - r * R;
-          for (int i = 0; i < nr; ++i) g[q] += (double)rows[i * R + r] * (double)rows[i * R + c];
-        }
+    int nrg = (int)blockDim.x / npairs;
+    if (nrg < 1) nrg = 1;
+    if (nrg > Ik) nrg = Ik;
+    __syncthreads();
+    for (int it = tid; it < npairs * nrg; it += blockDim.x) {
+      const int pr = it % npairs, rg = it / npairs;
+      int r = 0, rem = pr;
+      while (rem >= R - r) {
+        rem -= R - r;
+        ++r;
       }
+      const int cidx = r + rem;
+      const int i0 = (int)((int64_t)rg * Ik / nrg), i1 = (int)((int64_t)(rg + 1) * Ik / nrg);
+      double acc = 0.0;
+      for (int i = i0; i < i1; ++i)
+        acc += (double)A[(int64_t)i * R + r] * (double)A[(int64_t)i * R + cidx];
+      gpart[it] = acc;
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (tid + q * 1024 < R2) had[tid + q * 1024] *= g[q];
-    __syncthreads();
+    for (int pr = tid; pr < npairs; pr += blockDim.x) {
+      int r = 0, rem = pr;
+      while (rem >= R - r) {
+        rem -= R - r;
+        ++r;
+      }
+      const int cidx = r + rem;
+      double gsum2 = 0.0;
+      for (int rg = 0; rg < nrg; ++rg) gsum2 += gpart[rg * npairs + pr];
+      had[r * R + cidx] *= gsum2;
+      if (cidx != r) had[cidx * R + r] *= gsum2;
+    }
   }
-  // grad f = A^(n) H - M, M = sum of the partial MTTKRPs (fixed order)
+  __syncthreads();
+  // grad f = A^(n) H - M
   const CPD_GLOBAL float* An = gmem((const float*)dp->A[n]);
   double gsum = 0.0;
   for (int e = tid; e < In * R; e += blockDim.x) {
     const int i = e / R, r = e - i * R;
-    double m = 0.0;
-    for (int c = 0; c < nchunks; ++c) m += (double)partial[(int64_t)c * In * R + e];
+    const double m = M[e];
     double ah = 0.0;
     for (int s = 0; s < R; ++s) ah += (double)An[(int64_t)i * R + s] * had[s * R + r];
     const double gr = ah - m;
@@ -275,23 +346,34 @@ __global__ void __launch_bounds__(1024) variance_final_kernel(const ChainDesc* _
   }
 }
 
-// Scratch layout of one variance evaluation.
+// Scratch layout and launch shape of one variance evaluation.
 struct VarPlan {
-  int nchunks, nblocks;
-  size_t desc, state, cdf, partial, terms, out, total;
+  int ngroups, tpg, nchunks, nblocks;
+  int64_t J, rpc, rpb;
+  size_t lds;
+  size_t desc, state, cdf, part, rr, zw, M, terms, out, total;
 };
 
 static VarPlan plan_variance(const ChainDesc& d, int n) {
   VarPlan v;
-  int64_t J = 1;
+  v.J = 1;
   for (int k = 0; k < d.N; ++k)
-    if (k != n) J *= d.dims[k];
-  const int ntiles = (d.dims[n] + 15) / 16;
-  int64_t nch = (2048 + ntiles - 1) / ntiles;
-  const int64_t maxch = (J + 63) / 64;
-  v.nchunks = (int)(nch < 1 ? 1 : (nch > maxch ? maxch : nch));
-  int64_t nb = (J + 255) / 256;
+    if (k != n) v.J *= d.dims[k];
+  const int RT = (d.R + 15) / 16;
+  const int nct = (d.dims[n] + 15) / 16;
+  const int tmax = 4 * var_tiles_per_wave(RT);  // column tiles of one block
+  v.ngroups = (nct + tmax - 1) / tmax;
+  v.tpg = (nct + v.ngroups - 1) / v.ngroups;
+  v.lds = var_pass_lds(v.tpg, RT);
+  // about 1024 blocks, rows in whole 16-row tiles
+  int64_t nch = (1024 + v.ngroups - 1) / v.ngroups;
+  const int64_t tiles = (v.J + 15) / 16;
+  if (nch > tiles) nch = tiles;
+  v.rpc = (tiles + nch - 1) / nch * 16;
+  v.nchunks = (int)((v.J + v.rpc - 1) / v.rpc);
+  int64_t nb = (v.J + 1023) / 1024;
   v.nblocks = (int)(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
+  v.rpb = (v.J + v.nblocks - 1) / v.nblocks;
   size_t off = 0;
   auto take = [&](size_t b) {
     const size_t o = off;
@@ -303,11 +385,26 @@ static VarPlan plan_variance(const ChainDesc& d, int n) {
   v.desc = take(sizeof(ChainDesc));
   v.state = take(sizeof(ChainState) + 64);
   v.cdf = take(sizeof(double) * sumdims);
-  v.partial = take(sizeof(float) * (size_t)v.nchunks * d.dims[n] * d.R);
+  v.part = take(sizeof(float) * (size_t)v.nchunks * d.dims[n] * d.R);
+  v.rr = take(sizeof(double) * (size_t)v.ngroups * v.J);
+  v.zw = take(sizeof(double) * (size_t)v.J);
+  v.M = take(sizeof(double) * (size_t)d.dims[n] * d.R);
   v.terms = take(sizeof(double) * v.nblocks);
   v.out = take(sizeof(double) * 4);
   v.total = off;
   return v;
+}
+
+template <int RT>
+static hipError_t launch_pass(const VarPlan& v, const ChainDesc* dd, int n, char* scratch,
+                              hipStream_t stream) {
+  static std::atomic<uint32_t> attr{0};
+  hipError_t e = set_lds_limit_once((const void*)variance_pass_kernel<RT>, 160 * 1024, &attr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((variance_pass_kernel<RT>), dim3(v.nchunks, v.ngroups), dim3(kVpThreads),
+                     v.lds, stream, dd, n, v.rpc, v.tpg, (float*)(scratch + v.part),
+                     (double*)(scratch + v.rr), (double*)(scratch + v.zw));
+  return hipGetLastError();
 }
 
 cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_lds, int n,
@@ -345,13 +442,21 @@ cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_ld
     e = launch_chain_kernel(dd, 1, d.RT, lds, a, stream);
   }
   if (e != hipSuccess) return done(hip_fail(e, "refresh kernel"));
-  const int ntiles = (d.dims[n] + 15) / 16;
-  hipLaunchKernelGGL(variance_mttkrp_kernel, dim3(ntiles * v.nchunks), dim3(64), 0, stream, dd, n,
-                     v.nchunks, (float*)(scratch + v.partial));
-  hipLaunchKernelGGL(variance_terms_kernel, dim3(v.nblocks), dim3(64), 0, stream, dd, n,
-                     v.nblocks, (double*)(scratch + v.terms));
-  hipLaunchKernelGGL(variance_final_kernel, dim3(1), dim3(1024), 0, stream, dd, n, v.nchunks,
-                     (const float*)(scratch + v.partial), v.nblocks,
+  switch (d.RT) {
+    case 1: e = launch_pass<1>(v, dd, n, scratch, stream); break;
+    case 2: e = launch_pass<2>(v, dd, n, scratch, stream); break;
+    case 3: e = launch_pass<3>(v, dd, n, scratch, stream); break;
+    default: e = launch_pass<4>(v, dd, n, scratch, stream); break;
+  }
+  if (e != hipSuccess) return done(hip_fail(e, "variance pass kernel"));
+  const int E = d.dims[n] * d.R;
+  hipLaunchKernelGGL(variance_msum_kernel, dim3((E + 15) / 16), dim3(1024), 0, stream,
+                     (const float*)(scratch + v.part), v.nchunks, E, (double*)(scratch + v.M));
+  hipLaunchKernelGGL(variance_terms_kernel, dim3(v.nblocks), dim3(256), 0, stream,
+                     (const double*)(scratch + v.rr), (const double*)(scratch + v.zw), v.J,
+                     v.ngroups, v.rpb, (double*)(scratch + v.terms));
+  hipLaunchKernelGGL(variance_final_kernel, dim3(1), dim3(1024), 0, stream, dd, n,
+                     (const double*)(scratch + v.M), v.nblocks,
                      (const double*)(scratch + v.terms), (double*)(scratch + v.out));
   e = hipGetLastError();
   if (e != hipSuccess) return done(hip_fail(e, "variance kernels"));
