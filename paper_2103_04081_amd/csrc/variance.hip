@@ -38,14 +38,14 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 constexpr int kVpThreads = 256;  // threads of a pass block (four waves)
 
 // Column tiles of one wave held in registers for a rank-tile count RT.
-__host__ __device__ constexpr int var_tiles_per_wave(int rt) { return rt >= 4 ? 2 : 8 / rt; }
+__host__ __device__ constexpr int var_tiles_per_wave(int rt) { return rt == 1 ? 5 : (rt == 2 ? 4 : 2); }
 
 // LDS of a pass block: A^(n) rows of the group's columns (ranks padded to
-// 16 RT), the Z tile (16 rows, stride 16 RT + 1), row multi-indices, the
-// per-wave row sums.
+// 16 RT), two Z tiles (16 rows, stride 16 RT + 1) and the row multi-indices
+// of two tiles (the current one and the next), the per-wave row sums.
 __host__ __device__ inline size_t var_pass_lds(int tpg, int RT) {
-  return sizeof(float) * (size_t)tpg * 16 * 16 * RT + sizeof(float) * 16 * (16 * RT + 1) +
-         sizeof(int32_t) * 16 * kMaxModes + sizeof(double) * 4 * 16;
+  return sizeof(float) * (size_t)tpg * 16 * 16 * RT + 2 * sizeof(float) * 16 * (16 * RT + 1) +
+         2 * sizeof(int32_t) * 16 * kMaxModes + sizeof(double) * 4 * 16;
 }
 
 // Block (c, g): rows [c rpc, (c + 1) rpc) in 16-row tiles, column tiles
@@ -69,9 +69,9 @@ __global__ void __launch_bounds__(kVpThreads) variance_pass_kernel(
   const int64_t r0 = (int64_t)c * rpc, r1 = r0 + rpc < J ? r0 + rpc : J;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int gl = lane >> 4, cl = lane & 15;
-  float* As = (float*)vsm;                               // [tpg * 16][Rp]
-  float* Zt = As + (size_t)tpg * 16 * Rp;                // [16][ZS]
-  int32_t* ikl = (int32_t*)(Zt + 16 * ZS);               // [16][kMaxModes]
+  float* As = (float*)vsm;                                // [tpg * 16][Rp]
+  float* Zb = As + (size_t)tpg * 16 * Rp;                 // [2][16][ZS]
+  int32_t* ikb = (int32_t*)(Zb + 2 * 16 * ZS);            // [2][16][kMaxModes]
   double* red = (double*)(vsm + var_pass_lds(tpg, RT) - sizeof(double) * 4 * 16);  // [4][16]
   const CPD_GLOBAL float* An = gmem((const float*)dp->A[n]);
   for (int e = tid; e < tpg * 16 * Rp; e += kVpThreads) {
@@ -79,7 +79,17 @@ __global__ void __launch_bounds__(kVpThreads) variance_pass_kernel(
     As[e] = (i < In && r < R) ? An[(int64_t)i * R + r] : 0.f;
   }
   // row multi-index of row r0 + tid (threads 0..15), advanced by 16 per tile
+  // (odometer over the modes k != n, the lowest fastest)
   int ik[kMaxModes];
+  auto advance = [&]() {
+    int carry = 16;
+    for (int k = 0; k < N && carry; ++k) {
+      if (k == n) continue;
+      const int v = ik[k] + carry;
+      carry = v / dp->dims[k];
+      ik[k] = v - carry * dp->dims[k];
+    }
+  };
   if (tid < 16) {
     int64_t rem = r0 + tid;
     for (int k = 0; k < N; ++k) {
@@ -89,59 +99,58 @@ __global__ void __launch_bounds__(kVpThreads) variance_pass_kernel(
       ik[k] = (int)(rem - nx * dp->dims[k]);
       rem = nx;
     }
+    for (int k = 0; k < N; ++k) ikb[tid * kMaxModes + k] = ik[k];
+    advance();
+    for (int k = 0; k < N; ++k) ikb[(16 + tid) * kMaxModes + k] = ik[k];
+    advance();
   }
+  __syncthreads();
+  // z_j(r) = prod_{k != n} A^(k)(i_k, r), ascending k, for entry e of the
+  // tile starting at row tb whose indices are in buffer ib
+  constexpr int ZE = (16 * Rp + kVpThreads - 1) / kVpThreads;  // entries per thread
+  auto z_tile = [&](int64_t tb, int ib, float (&zv)[ZE]) {
+#pragma unroll
+    for (int u = 0; u < ZE; ++u) {
+      const int e = tid + u * kVpThreads;
+      const int row = e / Rp, r = e - row * Rp;
+      float z = 0.f;
+      if (e < 16 * Rp && tb + row < r1 && r < R) {
+        bool first = true;
+        for (int k = 0; k < N; ++k) {
+          if (k == n) continue;
+          const float a = gmem((const float*)dp->A[k])
+              [(int64_t)ikb[(ib * 16 + row) * kMaxModes + k] * R + r];
+          z = first ? a : z * a;
+          first = false;
+        }
+      }
+      zv[u] = z;
+    }
+  };
+  auto z_store = [&](int zbuf, const float (&zv)[ZE]) {
+#pragma unroll
+    for (int u = 0; u < ZE; ++u) {
+      const int e = tid + u * kVpThreads;
+      if (e < 16 * Rp) Zb[(zbuf * 16 + e / Rp) * ZS + e % Rp] = zv[u];
+    }
+  };
+  {
+    float zv[ZE];
+    z_tile(r0, 0, zv);
+    z_store(0, zv);
+  }
+  __syncthreads();
   vf4 macc[MT][RT];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) macc[m][rt] = vf4{0.f, 0.f, 0.f, 0.f};
   const int64_t ld = dp->ld[n];
-  for (int64_t t0 = r0; t0 < r1; t0 += 16) {
-    if (tid < 16) {
-      for (int k = 0; k < N; ++k) ikl[tid * kMaxModes + k] = ik[k];
-      // next tile: row + 16 (odometer over the modes k != n, lowest fastest)
-      int carry = 16;
-      for (int k = 0; k < N && carry; ++k) {
-        if (k == n) continue;
-        const int v = ik[k] + carry;
-        carry = v / dp->dims[k];
-        ik[k] = v - carry * dp->dims[k];
-      }
-    }
-    __syncthreads();
-    // the KRP rows of the tile: z_j(r) = prod_{k != n} A^(k)(i_k, r), ascending k
-    for (int e = tid; e < 16 * Rp; e += kVpThreads) {
-      const int row = e / Rp, r = e - row * Rp;
-      float z = 0.f;
-      if (t0 + row < r1 && r < R) {
-        bool first = true;
-        for (int k = 0; k < N; ++k) {
-          if (k == n) continue;
-          const float a = gmem((const float*)dp->A[k])[(int64_t)ikl[row * kMaxModes + k] * R + r];
-          z = first ? a : z * a;
-          first = false;
-        }
-      }
-      Zt[row * ZS + r] = z;
-    }
-    __syncthreads();
-    if (g == 0 && tid < 16 && t0 + tid < r1) {
-      // p_j: product over k != n of q / Q of the sampler's integer CDFs
-      double p = 1.0;
-      for (int k = 0; k < N; ++k) {
-        if (k == n) continue;
-        const CPD_GLOBAL double* C = gmem((const double*)dp->C[k]);
-        const int i = ikl[tid * kMaxModes + k];
-        const double Q = C[dp->dims[k] - 1];
-        p = p * ((C[i] - (i ? C[i - 1] : 0.0)) / Q);
-      }
-      float z2 = 0.f;
-      for (int r = 0; r < Rp; ++r) z2 = fmaf(Zt[tid * ZS + r], Zt[tid * ZS + r], z2);
-      zw[t0 + tid] = p > 0.0 ? (double)z2 / p : 0.0;
-    }
-    double r2[4] = {0.0, 0.0, 0.0, 0.0};
-    // all fibre values of the wave's column tiles first (one wait), then the
-    // matrix-core work tile by tile
+  int cur = 0;
+  for (int64_t t0 = r0; t0 < r1; t0 += 16, cur ^= 1) {
+    const float* Zt = Zb + cur * 16 * ZS;
+    // in flight together: this tile's fibre values, the next tile's factor
+    // rows, this tile's CDF entries
     float xs[MT][4];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
@@ -160,6 +169,23 @@ __global__ void __launch_bounds__(kVpThreads) variance_pass_kernel(
         xs[m][q] = v;
       }
     }
+    float zn[ZE];
+    z_tile(t0 + 16, cur ^ 1, zn);
+    if (g == 0 && tid < 16 && t0 + tid < r1) {
+      // p_j: product over k != n of q / Q of the sampler's integer CDFs
+      double p = 1.0;
+      for (int k = 0; k < N; ++k) {
+        if (k == n) continue;
+        const CPD_GLOBAL double* C = gmem((const double*)dp->C[k]);
+        const int i = ikb[(cur * 16 + tid) * kMaxModes + k];
+        const double Q = C[dp->dims[k] - 1];
+        p = p * ((C[i] - (i ? C[i - 1] : 0.0)) / Q);
+      }
+      float z2 = 0.f;
+      for (int r = 0; r < Rp; ++r) z2 = fmaf(Zt[tid * ZS + r], Zt[tid * ZS + r], z2);
+      zw[t0 + tid] = p > 0.0 ? (double)z2 / p : 0.0;
+    }
+    double r2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       const int ct = ct0 + wave + 4 * m;
@@ -185,6 +211,12 @@ __global__ void __launch_bounds__(kVpThreads) variance_pass_kernel(
         for (int q = 0; q < 4; ++q)
           macc[m][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Zt[(4 * gl + q) * ZS + rt * 16 + cl],
                                                              x[q], macc[m][rt], 0, 0, 0);
+    }
+    // the next tile's Z; the indices of the tile after it replace this tile's
+    z_store(cur ^ 1, zn);
+    if (tid < 16) {
+      for (int k = 0; k < N; ++k) ikb[(cur * 16 + tid) * kMaxModes + k] = ik[k];
+      advance();
     }
     // per-row sums over the columns: the 16 lanes of a group, then the waves
 #pragma unroll
