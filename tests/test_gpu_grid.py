@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle import philox
 from parity_util import gpu_decomposition, oracle_for, problem, rel, sample_from_cdfs
 
 pytestmark = pytest.mark.gpu
@@ -199,5 +200,52 @@ def test_grid_short_modes_split_fibre_range(dims, R, sampler, storage):
     A = g.factors()
     err = max(rel(A[k], orc.A[k]) for k in range(len(dims)))
     print(f"short modes, B = {B}: max rel err vs oracle {err:.3e}")
+    assert err <= 1e-5
+    g.close()
+
+
+def test_grid_max_batch():
+    """B = 2^20 (the library's largest batch, 2048 gather blocks), 24x20x16,
+    R 6.  Draws bit for bit against the oracle's Philox words and inverse CDF
+    at sampled fibres (the first and last 64, the ends of the first gather
+    blocks and the middle, where draw numbers reach 1 + 2 B); the
+    probabilities of all 2^20 fibres against the product of the CDF ratios;
+    the row counts of each mode within 6 sigma of B q_i / Q; then two
+    replayed steps against the oracle."""
+    import paper_2103_04081_amd.cpdmi as C
+    _announce("grid_max_batch")
+    dims, R, B, seed = (24, 20, 16), 6, C.MAX_BATCH, 9
+    prob = problem(dims, R)
+    g = gpu_decomposition(prob, B, sampler="euclidean", eta=0.3, seed=seed)
+    cdfs = [g.cdf(k) for k in range(3)]
+    n, idx, pr = g.sample(0)
+    assert n == O.mode_draw(seed, 0, 0, 3)
+    assert idx.shape == (B, 2)
+    modes = [k for k in range(3) if k != n]
+    p_all = np.ones(B)
+    for s, k in enumerate(modes):
+        Ck = cdfs[k]
+        Q = float(Ck[-1])
+        q = np.diff(np.concatenate([[0.0], Ck]))
+        assert idx[:, s].min() >= 0 and idx[:, s].max() < dims[k]
+        p_all = p_all * (q[idx[:, s]] / Q)
+        counts = np.bincount(idx[:, s], minlength=dims[k])
+        mean = B * q / Q
+        assert np.all(np.abs(counts - mean) <= 6.0 * np.sqrt(mean * (1 - q / Q)) + 1.0), k
+    assert np.array_equal(pr, p_all)
+    fibres = (list(range(64)) + [511, 512, 513, 1023, 1024, B // 2 - 1, B // 2]
+              + list(range(B - 64, B)))
+    for f in fibres:
+        for s, k in enumerate(modes):
+            u = philox.draw_word(seed, 0, 0, 1 + s * B + f)
+            assert idx[f, s] == O.inverse_cdf(cdfs[k], float(cdfs[k][-1]), u), (f, s)
+    orc = oracle_for(prob, B, sampler="euclidean", eta=0.3, seed=seed)
+    for t in range(2):
+        n, idx, _ = g.sample(t)
+        orc.step(replay=(n, idx))
+        g.step(1)
+    A = g.factors()
+    err = max(rel(A[k], orc.A[k]) for k in range(3))
+    print(f"B = 2^20: max rel err vs oracle after 2 steps {err:.3e}", flush=True)
     assert err <= 1e-5
     g.close()

@@ -307,3 +307,35 @@ def test_error_paths():
     with pytest.raises(P.CpdError):
         dec.fit()
     dec.close()
+
+
+def test_persistent_largest_batch_and_grid_beyond():
+    """24x20x16, R 6: B = 1280 is the largest batch whose step fits the
+    persistent kernel's LDS, and B = 1281 (padded to 1408 fibres) is run by
+    the grid step instead.  Both draw bit for bit what the oracle's sampler
+    draws from the device's CDFs and follow the oracle over 10 replayed
+    steps."""
+    import paper_2103_04081_amd as P
+    import paper_2103_04081_amd.cpdmi as C
+    _announce("persistent_largest_batch")
+    dims, R = (24, 20, 16), 6
+    prob = problem(dims, R)
+    P.cpd_workspace_size(P.make_problem(list(dims), R, 1280), C.make_options(path="persistent"))
+    with pytest.raises(Exception):
+        P.cpd_workspace_size(P.make_problem(list(dims), R, 1281),
+                             C.make_options(path="persistent"))
+    for B, path in ((1280, "persistent"), (1281, "grid")):
+        dec = gpu_decomposition(prob, B, sampler="euclidean", eta=0.3, path=path)
+        orc = oracle_for(prob, B, sampler="euclidean", eta=0.3)
+        for t in range(10):
+            cdfs = [dec.cdf(k) for k in range(3)]
+            n, idx, p = dec.sample(t)
+            n2, idx2, p2 = sample_from_cdfs(cdfs, 5, 0, t, B)
+            assert n == n2 and np.array_equal(idx, idx2) and np.array_equal(p, p2), (B, t)
+            orc.step(replay=(n, idx))
+            dec.step(1)
+        A = dec.factors()
+        err = max(rel(A[k], orc.A[k]) for k in range(3))
+        print(f"B = {B} ({path}): max rel err vs oracle after 10 steps {err:.3e}", flush=True)
+        assert err <= 1e-5
+        dec.close()
