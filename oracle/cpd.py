@@ -46,6 +46,13 @@ R6  Probabilities are recomputed from the current factors at every step.
 R7  fit = 1 - Tol with Tol the squared relative error of Section 5.2.
 R8  Nonnegative variant: project the updated factor onto A >= 0.
 R9  Decreasing step alpha_t = beta / (t + gamma) (Theorem 9).
+R10 Rescaling (the remark after the fixed-step error bound, Section 4.2,
+    which names no formula): rank component r is rescaled so that its N
+    columns all get the geometric mean of their norms, which leaves [[A]]
+    unchanged; a component with a zero or non-finite column norm is left as
+    it is.  The AdaGrad accumulators are not touched.  With rescaling every
+    k steps it follows the update of every k-th step, and the next draws use
+    the distributions of the rescaled factors (R6).
 """
 
 import math
@@ -246,7 +253,7 @@ class Oracle:
 
     def __init__(self, X, A0, *, B, sampler=EUCLIDEAN, rule=ADAGRAD, alpha=0.0,
                  eta=1.0, b=0.0, beta=0.0, gamma=1.0, seed=0, stream_id=0,
-                 nonneg=False):
+                 nonneg=False, rescale_every=0):
         self.X = np.asarray(X, dtype=np.float64)
         self.dims = list(self.X.shape)
         self.N = len(self.dims)
@@ -260,6 +267,7 @@ class Oracle:
         self.beta, self.gamma = float(beta), float(gamma)
         self.seed, self.stream_id = int(seed), int(stream_id)
         self.nonneg = bool(nonneg)
+        self.rescale_every = int(rescale_every)
         self.t = 0
         self.xnorm2 = float(np.sum(self.X * self.X))
 
@@ -342,6 +350,8 @@ class Oracle:
         G = self.gradient(n, idx, p)
         self.apply_update(n, G)
         self.t += 1
+        if self.rescale_every > 0 and self.t % self.rescale_every == 0:
+            self.A = rescale_columns(self.A)  # R10
         return n, idx, p
 
     def run(self, steps):
@@ -359,6 +369,23 @@ class Oracle:
 
     def full_gradient(self, n):
         return full_gradient(self.X, self.A, n)
+
+
+def rescale_columns(factors):
+    """Reading R10: for every rank component r with column norms
+    nu_k = ||A^(k)(:, r)|| (all positive and finite), scale column r of
+    factor k by g / nu_k, where g = (prod_k nu_k)^(1/N) is their geometric
+    mean.  The products of the scales are one, so [[A]] is unchanged."""
+    A = [np.array(a, dtype=np.float64, copy=True) for a in factors]
+    N, R = len(A), A[0].shape[1]
+    for r in range(R):
+        nu = [math.sqrt(float(np.sum(A[k][:, r] * A[k][:, r]))) for k in range(N)]
+        if not all(math.isfinite(v) and v > 0.0 for v in nu):
+            continue
+        g = math.prod(nu) ** (1.0 / N)
+        for k in range(N):
+            A[k][:, r] = A[k][:, r] * (g / nu[k])
+    return A
 
 
 def reconstruct(factors):

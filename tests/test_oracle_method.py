@@ -362,3 +362,66 @@ def test_planted_transposed_unfolding_is_caught():
     wrong = np.reshape(np.moveaxis(X, 1, 0), (4, -1), order="C")  # upper modes fastest
     j = O.column_index((2, 0, 3), [3, 4, 5], 1)
     assert wrong[0, j] != X[2, 0, 3]
+
+
+# ------------------------------------------------------------- rescaling ----
+
+def test_rescale_keeps_the_model_and_balances_norms():
+    """Reading R10 against what the mathematics fixes: the CP model is the
+    same tensor (compared through a brute-force reconstruction loop), every
+    component's columns end with equal norms equal to the geometric mean of
+    the old ones (computed as exp of the mean log), a second rescale changes
+    nothing, and leverage scores (invariant under column scaling) stay."""
+    rng = np.random.default_rng(3)
+    dims, R = (5, 4, 6), 3
+    As = [rng.standard_normal((I, R)) * rng.uniform(0.01, 50.0, size=R) for I in dims]
+    Bs = O.rescale_columns(As)
+    Xa = np.zeros(dims)
+    Xb = np.zeros(dims)
+    for i, j, k in itertools.product(*(range(I) for I in dims)):
+        for r in range(R):
+            Xa[i, j, k] += As[0][i, r] * As[1][j, r] * As[2][k, r]
+            Xb[i, j, k] += Bs[0][i, r] * Bs[1][j, r] * Bs[2][k, r]
+    assert rel_err(Xb, Xa) < 1e-13
+    for r in range(R):
+        old = [np.linalg.norm(A[:, r]) for A in As]
+        new = [np.linalg.norm(B[:, r]) for B in Bs]
+        g = math.exp(sum(math.log(v) for v in old) / len(old))
+        assert all(abs(v - g) <= 1e-12 * g for v in new)
+        # each column keeps its direction
+        for A, B in zip(As, Bs):
+            c = A[:, r] @ B[:, r] / (np.linalg.norm(A[:, r]) * np.linalg.norm(B[:, r]))
+            assert abs(c - 1.0) < 1e-14
+    Cs = O.rescale_columns(Bs)
+    assert all(rel_err(C, B) < 1e-14 for B, C in zip(Bs, Cs))
+    for A, B in zip(As, Bs):
+        assert np.allclose(O.leverage_scores(A), O.leverage_scores(B), rtol=1e-10, atol=1e-14)
+
+
+def test_rescale_leaves_degenerate_components():
+    """A component with a zero column keeps all of its columns as they were;
+    the other components are still balanced."""
+    rng = np.random.default_rng(4)
+    As = [rng.standard_normal((I, 2)) for I in (3, 4, 5)]
+    As[1][:, 0] = 0.0
+    Bs = O.rescale_columns(As)
+    for A, B in zip(As, Bs):
+        assert np.array_equal(A[:, 0], B[:, 0])
+    n1 = [np.linalg.norm(B[:, 1]) for B in Bs]
+    assert max(n1) - min(n1) <= 1e-12 * max(n1)
+
+
+def test_oracle_rescale_every_matches_manual_rescaling():
+    """rescale_every = k rescales after steps k, 2k, ...: the same draws
+    replayed into a plain oracle that is rescaled by hand at those steps
+    give the same iterates."""
+    X, As = _tiny(dims=(6, 5, 7), R=2, seed=5)
+    a = O.Oracle(X, As, B=6, sampler="euclidean", eta=0.2, seed=9, rescale_every=3)
+    b = O.Oracle(X, As, B=6, sampler="euclidean", eta=0.2, seed=9)
+    for t in range(9):
+        n, idx, _ = a.step()
+        b.step(replay=(n, idx))
+        if (t + 1) % 3 == 0:
+            b.A = O.rescale_columns(b.A)
+        assert all(rel_err(p, q) < 1e-13 for p, q in zip(a.A, b.A)), t
+    assert a.t == 9
