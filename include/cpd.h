@@ -116,6 +116,10 @@ typedef struct cpd_options {
                                       cpd_batch_member_info).  Results depend on it
                                       only through the FP32 summation order. */
   int32_t path;                    /* how a step is executed: CPD_PATH_* */
+  int32_t rescale_every;           /* k > 0: after every step that brings the step
+                                      counter t to a multiple of k, rescale the factor
+                                      columns as cpd_rescale does (single handles
+                                      only); 0 = never */
 } cpd_options;
 
 typedef struct cpd_handle cpd_handle;
@@ -178,6 +182,21 @@ CPD_API cpd_status cpd_step(cpd_handle* h, int64_t nsteps);
  * handle's current distributions.  Asynchronous like cpd_step.
  */
 CPD_API cpd_status cpd_step_replay(cpd_handle* h, int32_t mode, const int32_t* idx_dev);
+
+/*
+ * cpd_rescale: rescale the factor columns in place (the remark after the
+ * fixed-step error bound, Section 4.2, suggests scaling the factors after
+ * each iteration to keep them bounded; it gives no formula).  For every
+ * rank component r whose N column norms nu_k = ||A^(k)(:, r)|| are positive
+ * and finite, column r of factor k is multiplied by g / nu_k with g the
+ * geometric mean of the nu_k, so the CP model [[A]] is unchanged.  Other
+ * components are left as they are; the AdaGrad accumulators are not
+ * touched.  The sampling distributions of every mode are then rebuilt from
+ * the rescaled factors.  Norms and scales in FP64, factors in FP32.
+ * Asynchronous on the handle's stream; does nothing once the handle holds
+ * an error status.  Errors: CPD_E_INVALID (null handle), CPD_E_HIP.
+ */
+CPD_API cpd_status cpd_rescale(cpd_handle* h);
 
 /* Wait for the handle's stream; returns the handle's sticky device status. */
 CPD_API cpd_status cpd_sync(cpd_handle* h);

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcpdmi.so")
 
 SOURCES = ["cpd_api.hip", "step_kernel.hip", "layout_fit.hip", "batch_serve.hip", "serve.hip", "variance.hip",
-           "wide_step.hip"]
+           "wide_step.hip", "rescale.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

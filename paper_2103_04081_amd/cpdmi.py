@@ -54,7 +54,7 @@ class cpd_options(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("nonneg", ctypes.c_int32),
                 ("fit_every", ctypes.c_int32), ("fit_target", ctypes.c_double),
                 ("max_steps", ctypes.c_int64), ("ksplit", ctypes.c_int32 * MAX_MODES),
-                ("path", ctypes.c_int32)]
+                ("path", ctypes.c_int32), ("rescale_every", ctypes.c_int32)]
 
 
 class cpd_member_info(ctypes.Structure):
@@ -106,6 +106,7 @@ def lib():
                                 ctypes.c_void_p]),
             "cpd_step": (st, [H, ctypes.c_int64]),
             "cpd_step_replay": (st, [H, ctypes.c_int32, ctypes.c_void_p]),
+            "cpd_rescale": (st, [H]),
             "cpd_sync": (st, [H]),
             "cpd_fit": (st, [H, P(ctypes.c_double)]),
             "cpd_get_step": (st, [H, P(ctypes.c_int64)]),
@@ -179,7 +180,7 @@ def make_problem(dims, R, B, seed=0, stream_id=0):
 
 def make_options(sampler="euclidean", rule="adagrad", alpha=0.0, eta=1.0, b=0.0, beta=0.0,
                  gamma=1.0, storage="f32", nonneg=False, fit_every=25, fit_target=0.99,
-                 max_steps=0, ksplit=None, path="auto"):
+                 max_steps=0, ksplit=None, path="auto", rescale_every=0):
     o = cpd_options()
     o.sampler = SAMPLER[sampler] if isinstance(sampler, str) else int(sampler)
     o.rule = RULE[rule] if isinstance(rule, str) else int(rule)
@@ -192,6 +193,7 @@ def make_options(sampler="euclidean", rule="adagrad", alpha=0.0, eta=1.0, b=0.0,
     for k, v in enumerate(ksplit or []):
         o.ksplit[k] = int(v)
     o.path = PATH[path] if isinstance(path, str) else int(path)
+    o.rescale_every = int(rescale_every)
     return o
 
 
@@ -226,6 +228,10 @@ def cpd_step(h, nsteps):
 
 def cpd_step_replay(h, mode, idx_ptr):
     return check(lib().cpd_step_replay(h, int(mode), ctypes.c_void_p(idx_ptr)), "cpd_step_replay")
+
+
+def cpd_rescale(h):
+    return check(lib().cpd_rescale(h), "cpd_rescale")
 
 
 def cpd_sync(h):
@@ -475,7 +481,8 @@ class Decomposition:
 
     def __init__(self, X, A0, *, B, R=None, sampler="euclidean", rule="adagrad", alpha=0.0,
                  eta=1.0, b=0.0, beta=0.0, gamma=1.0, storage="f32", nonneg=False, seed=0,
-                 stream_id=0, device="cuda", dims=None, ksplit=None, path="auto"):
+                 stream_id=0, device="cuda", dims=None, ksplit=None, path="auto",
+                 rescale_every=0):
         self.device = torch.device(device)
         if isinstance(X, torch.Tensor):
             assert X.is_cuda and X.is_contiguous()
@@ -496,7 +503,7 @@ class Decomposition:
         self.dims, self.R, self.B = dims, R, int(B)
         self.problem = make_problem(dims, R, B, seed, stream_id)
         self.options = make_options(sampler, rule, alpha, eta, b, beta, gamma, storage, nonneg,
-                                    ksplit=ksplit, path=path)
+                                    ksplit=ksplit, path=path, rescale_every=rescale_every)
         self.ws_bytes = cpd_workspace_size(self.problem, self.options)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
@@ -545,6 +552,11 @@ class Decomposition:
         idx_t = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32), device=self.device)
         cpd_step_replay(self.h, mode, idx_t.data_ptr())
         self.sync()
+
+    def rescale(self):
+        """Balance every rank component's column norms across the modes
+        (the CP model is unchanged) and rebuild the distributions."""
+        cpd_rescale(self.h)
 
     def variance(self, n, sampler):
         """Exact variance of the sampled gradient of mode n under ``sampler``."""

@@ -90,6 +90,10 @@ cpd_status plan_batch(const cpd_problem* ps, const cpd_options* os, int count,
             std::to_string(CPD_MAX_PERSISTENT_BATCH) + ", LDS within 160 KiB)";
       s = CPD_E_INVALID;
     }
+    if (s == CPD_OK && os[i].rescale_every != 0) {
+      why = "rescale_every applies to single handles only (must be 0 in a batch)";
+      s = CPD_E_INVALID;
+    }
     if (s != CPD_OK) {
       set_error("member " + std::to_string(i) + ": " + why);
       return s;

@@ -48,6 +48,10 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
     *why = "path must be CPD_PATH_AUTO, CPD_PATH_PERSISTENT or CPD_PATH_GRID";
     return CPD_E_INVALID;
   }
+  if (o->rescale_every < 0) {
+    *why = "rescale_every must be >= 0";
+    return CPD_E_INVALID;
+  }
   int64_t total = 1;
   for (int k = 0; k < p->N; ++k) {
     if (p->dims[k] < 1 || p->dims[k] > CPD_MAX_DIM) {
@@ -300,6 +304,9 @@ struct cpd_handle {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // step counter as issued from the host (steps of cpd_step / cpd_step_replay
+  // since init or the last cpd_write_state): where rescale_every falls
+  int64_t t_host = 0;
 };
 
 static constexpr int kGridGraphSteps = 16;
@@ -563,13 +570,8 @@ cpd_status cpd_sample(cpd_handle* h, uint64_t t, int32_t* mode, int32_t* idx_dev
   return device_status(h);
 }
 
-cpd_status cpd_step(cpd_handle* h, int64_t nsteps) {
-  if (!h || nsteps < 0) {
-    set_error("bad argument");
-    return CPD_E_INVALID;
-  }
-  cpd_status s = set_device(h);
-  if (s != CPD_OK) return s;
+static cpd_status step_plain(cpd_handle* h, int64_t nsteps) {
+  cpd_status s = CPD_OK;
   if (h->plan.grid) {
     // whole groups of steps as graph replays (three launches per step would
     // otherwise be bound by the host), the rest launched directly
@@ -599,6 +601,54 @@ cpd_status cpd_step(cpd_handle* h, int64_t nsteps) {
   return CPD_OK;
 }
 
+// Column rescaling, then the distributions of every mode from the
+// rescaled factors.
+static cpd_status rescale_now(cpd_handle* h) {
+  hipError_t e = launch_rescale(h->d_desc, h->p.R, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "rescale kernel");
+  e = refresh_all(h);
+  if (e != hipSuccess) return hip_fail(e, "refresh kernel");
+  return CPD_OK;
+}
+
+cpd_status cpd_step(cpd_handle* h, int64_t nsteps) {
+  if (!h || nsteps < 0) {
+    set_error("bad argument");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  const int64_t k = h->o.rescale_every;
+  if (k <= 0) {
+    s = step_plain(h, nsteps);
+    if (s == CPD_OK) h->t_host += nsteps;
+    return s;
+  }
+  // runs of steps up to the next multiple of k, each followed by a rescale
+  for (int64_t done = 0; done < nsteps;) {
+    const int64_t run = std::min(nsteps - done, k - h->t_host % k);
+    s = step_plain(h, run);
+    if (s != CPD_OK) return s;
+    h->t_host += run;
+    done += run;
+    if (h->t_host % k == 0) {
+      s = rescale_now(h);
+      if (s != CPD_OK) return s;
+    }
+  }
+  return CPD_OK;
+}
+
+cpd_status cpd_rescale(cpd_handle* h) {
+  if (!h) {
+    set_error("null handle");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  return rescale_now(h);
+}
+
 cpd_status cpd_step_replay(cpd_handle* h, int32_t mode, const int32_t* idx_dev) {
   if (!h || !idx_dev || mode < 0 || mode >= h->p.N) {
     set_error("bad argument");
@@ -622,6 +672,8 @@ cpd_status cpd_step_replay(cpd_handle* h, int32_t mode, const int32_t* idx_dev) 
     e = launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
   }
   if (e != hipSuccess) return hip_fail(e, "replay kernel");
+  h->t_host += 1;
+  if (h->o.rescale_every > 0 && h->t_host % h->o.rescale_every == 0) return rescale_now(h);
   return CPD_OK;
 }
 
@@ -786,6 +838,7 @@ cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes) {
   }
   ChainState st{};
   st.t = hd.t;
+  h->t_host = hd.t;
   hipError_t e = hipMemcpyAsync(h->ws + h->plan.state, &st, sizeof(int64_t) + sizeof(int32_t),
                                 hipMemcpyHostToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(state t)");

@@ -41,6 +41,9 @@ hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nb
                               const WideInfo* info, int max_entries, hipStream_t stream);
 hipError_t launch_wide_refresh(const ChainDesc* d_desc, int rt, size_t lds_bytes,
                                const WideInfo* info, int mode, hipStream_t stream);
+// Column rescaling of every factor (rescale.hip): one block per rank
+// component, R blocks.
+hipError_t launch_rescale(const ChainDesc* d_desc, int R, hipStream_t stream);
 // Sets the dynamic-LDS limits of the grid kernels for (rt, dtype); called
 // before any of them is captured into a graph.
 hipError_t prepare_wide_kernels(int rt, int dtype);

@@ -532,6 +532,10 @@ cpd_status cpd_submit(cpd_server* s, const cpd_request* r, uint64_t* ticket) {
             std::to_string(CPD_MAX_PERSISTENT_BATCH) + ", LDS within 160 KiB)";
       st = CPD_E_INVALID;
     }
+    if (st == CPD_OK && r->options.rescale_every != 0) {
+      why = "rescale_every applies to single handles only (must be 0 for a served request)";
+      st = CPD_E_INVALID;
+    }
     if (st != CPD_OK) {
       set_error(why);
       return st;

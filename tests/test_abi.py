@@ -129,3 +129,18 @@ def test_batch_workspace_size():
     with pytest.raises(P.CpdError) as e:
         P.cpd_batch_workspace_size(bad, os_)
     assert "member 1" in str(e.value)
+
+
+def test_rescale_option_validation():
+    import paper_2103_04081_amd as P
+    p = P.make_problem([30, 20, 10], 4, 64)
+    P.cpd_workspace_size(p, P.make_options(rescale_every=1))
+    with pytest.raises(P.CpdError) as e:
+        P.cpd_workspace_size(p, P.make_options(rescale_every=-1))
+    assert "rescale_every" in str(e.value)
+    # batched members are single-round persistent steps: no rescaling
+    ps = [p, p]
+    P.cpd_batch_workspace_size(ps, [P.make_options(), P.make_options()])
+    with pytest.raises(P.CpdError) as e:
+        P.cpd_batch_workspace_size(ps, [P.make_options(), P.make_options(rescale_every=5)])
+    assert "member 1" in str(e.value) and "rescale_every" in str(e.value)
