@@ -90,6 +90,7 @@ def parse():
                     help="run only the serving section (profiling)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--no-grid", action="store_true", help="skip the large-batch grid sweep")
+    ap.add_argument("--no-rescale", action="store_true", help="skip the rescaling-cost section")
     ap.add_argument("--grid-only", action="store_true",
                     help="run only the large-batch grid sweep (profiling)")
     ap.add_argument("--grid-b", default="4096,16384,65536,131072,262144",
@@ -274,6 +275,8 @@ def main():
         extra["batch"] = batch_bench(args.batch_count, seq=not args.no_seq)
     extra["small_workload"] = small_workload()
     extra["four_way"] = four_way()
+    if not args.no_rescale:
+        extra["rescale"] = rescale_cost(w, X32)
     if not args.no_grid:
         extra["grid_sweep"] = grid_sweep(w, X32, args)
     if not args.no_variance:
@@ -543,6 +546,40 @@ def four_way(steps=2000):
                         "fit_after": dec.fit()}
         dec.close()
     del X
+    return out
+
+
+def rescale_cost(w, X32, steps=2000):
+    """Column rescaling between steps on the main 300^3 workload (persistent
+    step): steps/s without it, rescaling after every step and after every
+    25th, the fit after the run, and the cost of one cpd_rescale (the
+    rescale kernel plus the rebuild of every mode's CDF)."""
+    import torch
+
+    import paper_2103_04081_amd as P
+    out = {"workload": "300x300x300 FP32 tensor of the main workload, R=10, B=256, Euclidean "
+                       f"sampler, AdaGrad eta={ETA}; {steps} steps from the initial factors"}
+
+    def timed(dec, fn):
+        dec.sync()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(dec.stream)
+        fn()
+        ev1.record(dec.stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    for every in (0, 25, 1):
+        dec = P.Decomposition(X32, w["A0"], B=256, sampler="euclidean", rule="adagrad", eta=ETA,
+                              storage="f32", seed=w["seed"], rescale_every=every)
+        ms = timed(dec, lambda: dec.step(steps)) / steps
+        out[f"every_{every}"] = {"steps_per_s": 1e3 / ms, "us_per_step": ms * 1e3,
+                                 "fit_after": dec.fit()}
+        if every == 0:
+            n = 200
+            out["us_per_rescale"] = timed(dec, lambda: [dec.rescale() for _ in range(n)]) * 1e3 / n
+        dec.close()
     return out
 
 
