@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--no-grid", action="store_true", help="skip the large-batch grid sweep")
     ap.add_argument("--no-rescale", action="store_true", help="skip the rescaling-cost section")
+    ap.add_argument("--rescale-only", action="store_true",
+                    help="run only the rescaling-cost section (profiling)")
     ap.add_argument("--grid-only", action="store_true",
                     help="run only the large-batch grid sweep (profiling)")
     ap.add_argument("--grid-b", default="4096,16384,65536,131072,262144",
@@ -235,6 +237,9 @@ def main():
     w = ci.workload(2)
     dims, R, B = w["dims"], w["R"], w["B"]
     X32 = np.asfortranarray(w["X"].astype(np.float32))
+    if args.rescale_only:
+        print(json.dumps({"rescale": rescale_cost(w, X32)}), flush=True)
+        return
     if args.grid_only:
         out = {"grid_sweep": grid_sweep(w, X32, args)}
         calib_copy(args.calib_copy_mb)

@@ -14,7 +14,7 @@ namespace cpdmi {
 constexpr int kRescaleThreads = 256;
 
 __global__ void __launch_bounds__(kRescaleThreads) rescale_kernel(const ChainDesc* __restrict__ dp) {
-  __shared__ double red[kRescaleThreads];
+  __shared__ double red[kMaxModes][kRescaleThreads];
   __shared__ double scale[kMaxModes];
   __shared__ int go;
   const int tid = threadIdx.x, r = blockIdx.x;
@@ -22,26 +22,31 @@ __global__ void __launch_bounds__(kRescaleThreads) rescale_kernel(const ChainDes
   if (tid == 0) go = dp->state->status == 0;
   __syncthreads();
   if (!go) return;
-  for (int k = 0; k < N; ++k) {
-    const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]);
+  // squared column norms of all modes at once: every mode's loads are in
+  // flight together, then one tree over the N partial sums
+#pragma unroll
+  for (int k = 0; k < kMaxModes; ++k) {
     double s = 0.0;
-    for (int i = tid; i < dp->dims[k]; i += kRescaleThreads) {
-      const double v = Ak[(int64_t)i * R + r];
-      s += v * v;
+    if (k < N) {
+      const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]);
+      for (int i = tid; i < dp->dims[k]; i += kRescaleThreads) {
+        const double v = Ak[(int64_t)i * R + r];
+        s += v * v;
+      }
     }
-    red[tid] = s;
-    __syncthreads();
-    for (int h = kRescaleThreads / 2; h > 0; h >>= 1) {
-      if (tid < h) red[tid] += red[tid + h];
-      __syncthreads();
-    }
-    if (tid == 0) scale[k] = sqrt(red[0]);
+    red[k][tid] = s;
+  }
+  __syncthreads();
+  for (int h = kRescaleThreads / 2; h > 0; h >>= 1) {
+    if (tid < h)
+      for (int k = 0; k < N; ++k) red[k][tid] += red[k][tid + h];
     __syncthreads();
   }
   if (tid == 0) {
     bool ok = true;
     double prod = 1.0;
     for (int k = 0; k < N; ++k) {
+      scale[k] = sqrt(red[k][0]);
       ok = ok && isfinite(scale[k]) && scale[k] > 0.0;
       prod *= scale[k];
     }
