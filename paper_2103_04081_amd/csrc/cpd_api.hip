@@ -100,6 +100,11 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
     }
     w->wide_fb = fb;
     w->wide_blocks = (p->B + fb - 1) / fb;
+  } else {
+    // the all-mode CDF rebuild (init, state writes, rescaling) uses the grid
+    // path's one-block-per-mode refresh where its LDS plan fits
+    const size_t rl = refresh_plan(p->N, p->dims, p->R, RT).total;
+    w->refresh_lds = rl <= kLdsBudget ? rl : 0;
   }
   for (int k = 0; k < p->N; ++k) {
     const int ks = o->ksplit[k];
@@ -313,8 +318,12 @@ static constexpr int kGridGraphSteps = 16;
 
 // The distributions of every mode from the current factors.
 static hipError_t refresh_all(cpd_handle* h) {
-  if (h->plan.grid)
-    return launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, nullptr, -1, h->stream);
+  // one block per mode where the refresh kernel's LDS plan fits (it always
+  // does on the grid path), else the step kernel's own refresh in one block;
+  // both run the same refresh code, so the CDFs are the same
+  if (h->plan.refresh_lds > 0)
+    return launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, nullptr, -1, h->p.N,
+                               h->stream);
   StepArgs a{};
   a.op = OP_REFRESH;
   return launch_chain_kernel(h->d_desc, 1, h->desc.RT, h->plan.lds, a, h->stream);
@@ -336,7 +345,8 @@ static hipError_t wide_finish(cpd_handle* h, const WideArgs& a) {
   hipError_t e = launch_wide_update(h->d_desc, a.part, h->plan.wide_blocks, h->plan.wide_fb,
                                     a.info, imax * h->p.R, h->stream);
   if (e != hipSuccess || h->o.sampler == CPD_SAMPLER_UNIFORM) return e;
-  return launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, a.info, -2, h->stream);
+  return launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, a.info, -2, 1,
+                             h->stream);
 }
 
 static hipError_t wide_steps(cpd_handle* h, int64_t nsteps, hipStream_t stream) {
@@ -350,7 +360,7 @@ static hipError_t wide_steps(cpd_handle* h, int64_t nsteps, hipStream_t stream) 
       e = launch_wide_update(h->d_desc, a.part, h->plan.wide_blocks, h->plan.wide_fb, a.info,
                              imax * h->p.R, stream);
     if (e == hipSuccess && h->o.sampler != CPD_SAMPLER_UNIFORM)
-      e = launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, a.info, -2, stream);
+      e = launch_wide_refresh(h->d_desc, h->desc.RT, h->plan.refresh_lds, a.info, -2, 1, stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

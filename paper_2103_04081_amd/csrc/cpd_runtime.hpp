@@ -34,13 +34,13 @@ hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_tables, int nch
 // Grid-wide step (wide_step.hip).  Gather: nblocks slices of a.fb fibres,
 // wide_kparts parts of -G^T each; update: the parts of every entry of mode n summed
 // and applied (launched over max_rows * R entries); refresh: the CDF of mode `mode` (-1: every
-// mode, -2: the mode in info).
+// one of the nmodes modes, one block each; -2: the mode in info).
 hipError_t launch_wide_gather(const ChainDesc* d_desc, int rt, int dtype, int nblocks,
                               size_t lds_bytes, const WideArgs& a, hipStream_t stream);
 hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nblocks, int fb,
                               const WideInfo* info, int max_entries, hipStream_t stream);
 hipError_t launch_wide_refresh(const ChainDesc* d_desc, int rt, size_t lds_bytes,
-                               const WideInfo* info, int mode, hipStream_t stream);
+                               const WideInfo* info, int mode, int nmodes, hipStream_t stream);
 // Column rescaling of every factor (rescale.hip): one block per rank
 // component, R blocks.
 hipError_t launch_rescale(const ChainDesc* d_desc, int R, hipStream_t stream);

@@ -491,7 +491,7 @@ cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_ld
   e = hipMemcpyAsync(dd, &d, sizeof d, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return done(hip_fail(e, "hipMemcpyAsync(desc)"));
   if (grid_refresh_lds > 0) {
-    e = launch_wide_refresh(dd, d.RT, grid_refresh_lds, nullptr, -1, stream);
+    e = launch_wide_refresh(dd, d.RT, grid_refresh_lds, nullptr, -1, d.N, stream);
   } else {
     StepArgs a{};
     a.op = OP_REFRESH;

@@ -458,8 +458,8 @@ __global__ void __launch_bounds__(64 * kUpdWaves) wide_update_kernel(
   if (blockIdx.x == 0 && threadIdx.x == 0) st->t = t + 1;
 }
 
-// CDF of one mode (mode >= 0), of every mode (-1) or of the mode of the
-// step in flight (-2, after its update).
+// CDF of one mode (mode >= 0), of every mode (-1, one block per mode) or of
+// the mode of the step in flight (-2, after its update).
 template <int RT>
 __global__ void __launch_bounds__(kBlock) wide_refresh_kernel(const ChainDesc* __restrict__ dp,
                                                               const WideInfo* __restrict__ info,
@@ -493,8 +493,9 @@ __global__ void __launch_bounds__(kBlock) wide_refresh_kernel(const ChainDesc* _
     const int i = e / padc;
     mbuf[i * P.ms + R + (e - i * padc)] = 0.f;
   }
-  const int nb = mode >= 0 ? mode : (mode == -1 ? 0 : ninfo);
-  const int ne = mode == -1 ? N : nb + 1;
+  // mode -1: one block per mode
+  const int nb = mode >= 0 ? mode : (mode == -1 ? (int)blockIdx.x : ninfo);
+  const int ne = nb + 1;
   int err = 0;
   for (int n = nb; n < ne && !err; ++n) {
     const CPD_GLOBAL float* An = gmem(dp->A[n]);
@@ -570,20 +571,22 @@ hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nb
 
 template <int RT>
 static hipError_t refresh_rt(const ChainDesc* d, size_t lds, const WideInfo* info, int mode,
-                             hipStream_t s) {
+                             int nmodes, hipStream_t s) {
   hipError_t e = refresh_attr<RT>();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(wide_refresh_kernel<RT>, dim3(1), dim3(kBlock), lds, s, d, info, mode);
+  const int grid = mode == -1 ? nmodes : 1;
+  hipLaunchKernelGGL(wide_refresh_kernel<RT>, dim3(grid), dim3(kBlock), lds, s, d, info, mode);
   return hipGetLastError();
 }
 
 hipError_t launch_wide_refresh(const ChainDesc* d_desc, int rt, size_t lds_bytes,
-                               const WideInfo* info, int mode, hipStream_t stream) {
+                               const WideInfo* info, int mode, int nmodes, hipStream_t stream) {
+  if (mode == -1 && (nmodes < 1 || nmodes > kMaxModes)) return hipErrorInvalidValue;
   switch (rt) {
-    case 1: return refresh_rt<1>(d_desc, lds_bytes, info, mode, stream);
-    case 2: return refresh_rt<2>(d_desc, lds_bytes, info, mode, stream);
-    case 3: return refresh_rt<3>(d_desc, lds_bytes, info, mode, stream);
-    default: return refresh_rt<4>(d_desc, lds_bytes, info, mode, stream);
+    case 1: return refresh_rt<1>(d_desc, lds_bytes, info, mode, nmodes, stream);
+    case 2: return refresh_rt<2>(d_desc, lds_bytes, info, mode, nmodes, stream);
+    case 3: return refresh_rt<3>(d_desc, lds_bytes, info, mode, nmodes, stream);
+    default: return refresh_rt<4>(d_desc, lds_bytes, info, mode, nmodes, stream);
   }
 }
 
