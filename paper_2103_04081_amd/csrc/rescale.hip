@@ -12,6 +12,7 @@
 namespace cpdmi {
 
 constexpr int kRescaleThreads = 256;
+constexpr int kRescaleHeld = 2;  // column entries per thread kept in registers
 
 __global__ void __launch_bounds__(kRescaleThreads) rescale_kernel(const ChainDesc* __restrict__ dp) {
   __shared__ double red[kMaxModes][kRescaleThreads];
@@ -19,17 +20,32 @@ __global__ void __launch_bounds__(kRescaleThreads) rescale_kernel(const ChainDes
   __shared__ int go;
   const int tid = threadIdx.x, r = blockIdx.x;
   const int N = dp->N, R = dp->R;
+  // the sticky status is read together with the columns; nothing is
+  // written unless it is clear
   if (tid == 0) go = dp->state->status == 0;
-  __syncthreads();
-  if (!go) return;
   // squared column norms of all modes at once: every mode's loads are in
-  // flight together, then one tree over the N partial sums
+  // flight together (the first kRescaleHeld entries of each thread stay in
+  // registers for the scale pass), then one tree over the N partial sums
+  float held[kMaxModes][kRescaleHeld];
 #pragma unroll
   for (int k = 0; k < kMaxModes; ++k) {
     double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < kRescaleHeld; ++j) held[k][j] = 0.f;
     if (k < N) {
       const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]);
-      for (int i = tid; i < dp->dims[k]; i += kRescaleThreads) {
+      const int I = dp->dims[k];
+#pragma unroll
+      for (int j = 0; j < kRescaleHeld; ++j) {
+        const int i = tid + j * kRescaleThreads;
+        if (i < I) held[k][j] = Ak[(int64_t)i * R + r];
+      }
+#pragma unroll
+      for (int j = 0; j < kRescaleHeld; ++j) {
+        const double v = held[k][j];
+        s += v * v;
+      }
+      for (int i = tid + kRescaleHeld * kRescaleThreads; i < I; i += kRescaleThreads) {
         const double v = Ak[(int64_t)i * R + r];
         s += v * v;
       }
@@ -43,7 +59,7 @@ __global__ void __launch_bounds__(kRescaleThreads) rescale_kernel(const ChainDes
     __syncthreads();
   }
   if (tid == 0) {
-    bool ok = true;
+    bool ok = go != 0;
     double prod = 1.0;
     for (int k = 0; k < N; ++k) {
       scale[k] = sqrt(red[k][0]);
@@ -57,10 +73,20 @@ __global__ void __launch_bounds__(kRescaleThreads) rescale_kernel(const ChainDes
   }
   __syncthreads();
   if (!go) return;
-  for (int k = 0; k < N; ++k) {
-    CPD_GLOBAL float* Ak = gmem(dp->A[k]);
-    const float sk = (float)scale[k];
-    for (int i = tid; i < dp->dims[k]; i += kRescaleThreads) Ak[(int64_t)i * R + r] *= sk;
+#pragma unroll
+  for (int k = 0; k < kMaxModes; ++k) {
+    if (k < N) {
+      CPD_GLOBAL float* Ak = gmem(dp->A[k]);
+      const int I = dp->dims[k];
+      const float sk = (float)scale[k];
+#pragma unroll
+      for (int j = 0; j < kRescaleHeld; ++j) {
+        const int i = tid + j * kRescaleThreads;
+        if (i < I) Ak[(int64_t)i * R + r] = held[k][j] * sk;
+      }
+      for (int i = tid + kRescaleHeld * kRescaleThreads; i < I; i += kRescaleThreads)
+        Ak[(int64_t)i * R + r] *= sk;
+    }
   }
 }
 
