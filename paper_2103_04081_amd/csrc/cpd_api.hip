@@ -866,8 +866,9 @@ cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, double* out) 
   if (s != CPD_OK) return s;
   s = device_status(h);
   if (s != CPD_OK) return s;
-  return variance_eval(h->desc, h->plan.lds, h->plan.grid ? h->plan.refresh_lds : 0, n, sampler,
-                       h->stream, out);
+  // the sampler's CDFs are rebuilt one block per mode where that kernel's
+  // LDS plan fits (always on the grid path)
+  return variance_eval(h->desc, h->plan.lds, h->plan.refresh_lds, n, sampler, h->stream, out);
 }
 
 cpd_status cpd_destroy(cpd_handle* h) {

@@ -81,7 +81,8 @@ void describe_status(cpd_status s);
 
 // Exact variance of the sampled gradient of mode n (variance.hip).
 // grid_refresh_lds > 0: the distributions are rebuilt by the grid path's
-// refresh kernel (with that LDS) instead of the persistent kernel.
+// refresh kernel (one block per mode, with that LDS) instead of the
+// persistent kernel.
 cpd_status variance_eval(const ChainDesc& host_desc, size_t lds, size_t grid_refresh_lds, int n,
                          int sampler, hipStream_t stream, double* out3);
 
