@@ -170,9 +170,12 @@ CPD_API cpd_status cpd_sample(cpd_handle* h, uint64_t t, int32_t* mode, int32_t*
 
 /*
  * cpd_step: enqueue nsteps steps (t .. t+nsteps-1) on the handle's stream
- * (one persistent launch, or three launches per step on the GRID path).  Asynchronous: a non-finite factor or a sampling
- * failure is recorded on the device and reported by the next synchronising
- * call (cpd_sync, cpd_fit, cpd_read_*).
+ * (one persistent launch, or three launches per step on the GRID path).
+ * With rescale_every = k > 0 the steps run in stretches that end where t
+ * reaches a multiple of k, each followed by the two launches of
+ * cpd_rescale.  Asynchronous: a non-finite factor or a sampling failure is
+ * recorded on the device and reported by the next synchronising call
+ * (cpd_sync, cpd_fit, cpd_read_*).
  */
 CPD_API cpd_status cpd_step(cpd_handle* h, int64_t nsteps);
 
