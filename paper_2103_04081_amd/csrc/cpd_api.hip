@@ -612,10 +612,11 @@ static cpd_status step_plain(cpd_handle* h, int64_t nsteps) {
 }
 
 // Column rescaling, then the distributions of every mode from the
-// rescaled factors.
+// rescaled factors (uniform ones do not depend on them).
 static cpd_status rescale_now(cpd_handle* h) {
   hipError_t e = launch_rescale(h->d_desc, h->p.R, h->stream);
   if (e != hipSuccess) return hip_fail(e, "rescale kernel");
+  if (h->o.sampler == CPD_SAMPLER_UNIFORM) return CPD_OK;
   e = refresh_all(h);
   if (e != hipSuccess) return hip_fail(e, "refresh kernel");
   return CPD_OK;
