@@ -93,3 +93,42 @@ def test_rescale_every_replay_against_oracle(case):
     assert abs(dec.fit() - orc.fit()) <= 1e-5
     assert dec.t == 20
     dec.close()
+
+
+@pytest.mark.parametrize("path,B,every,total,cut", [("persistent", 40, 3, 20, 7),
+                                                    ("grid", 300, 17, 40, 7)])
+def test_rescale_schedule_across_calls_and_state(path, B, every, total, cut):
+    """The rescaling points depend on the step counter only: all steps in
+    one cpd_step call (stretches of `every` steps between rescales; on the
+    grid path a 17-step stretch is a 16-step graph replay plus one direct
+    step), single-step calls, and `cut` steps saved and resumed by a fresh
+    handle for the rest all give the same factors, bit for bit."""
+    import paper_2103_04081_amd as P
+    print("CASE rescale_schedule", path, every, flush=True)
+    dims, R = (37, 45, 53), 7
+    prob = _unbalanced(dims, R)
+    X32 = np.asfortranarray(prob["X"].astype(np.float32))
+
+    def make():
+        return P.Decomposition(X32, prob["A0"], B=B, sampler="euclidean", eta=0.3, seed=5,
+                               path=path, rescale_every=every)
+
+    a = make()
+    a.step(total)
+    b = make()
+    for _ in range(total):
+        b.step(1)
+    c = make()
+    c.step(cut)
+    blob = c.state()
+    c.close()
+    d = make()
+    d.load_state(blob)
+    d.step(total - cut)
+    A, Bf, D = a.factors(), b.factors(), d.factors()
+    assert a.t == b.t == d.t == total
+    for k in range(3):
+        assert np.array_equal(A[k], Bf[k]), k
+        assert np.array_equal(A[k], D[k]), k
+    for h in (a, b, d):
+        h.close()
