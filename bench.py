@@ -313,7 +313,11 @@ def main():
                      "traffic": (None if traffic is None else traffic * args.steps),
                      "traffic_per_step": traffic, "bytes_per_step": sb,
                      "steps_per_launch": args.steps, "kernel": "chain_kernel<1>",
-                     "counters": MEASURED_TRAFFIC["profile"]},
+                     "counters": MEASURED_TRAFFIC["profile"],
+                     "note": "one decomposition's steps form a dependent chain (the CDF of step "
+                             "t's mode feeds the draws of step t+1), run by one workgroup: "
+                             "latency-bound; grid_sweep and batch carry the bandwidth-bound "
+                             "forms of the same step"},
         "fit_after_timed_steps": fit_after,
     }
     out.update(extra)
