@@ -242,12 +242,17 @@ CPD_API cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes)
  * residual of fibre j, p_j = prod_{k != n} q_k(i_k) / Q_k the probability of
  * the integer-valued distributions the sampler builds from the current
  * factors, and grad f = A^(n) (hadamard_{k != n} A^(k)T A^(k)) - X_(n) Z^(n).
- * Two passes over copy n; FP32 products, FP64 sums.  Synchronous; uses
- * temporary device memory (about 128 KiB * R for the partial sums, plus the
- * distributions).  The handle's state is not changed.
- * Errors: CPD_E_INVALID, CPD_E_RANK_DEFICIENT (leverage), CPD_E_HIP.
+ * One pass over copy n; FP32 products, FP64 sums.
+ *   ws        caller-owned device scratch of at least
+ *             cpd_variance_workspace_size(h, n) bytes, 256-byte aligned,
+ *             used only during the call (no allocation inside the call).
+ * Synchronous on the handle's stream.  The handle's state is not changed.
+ * Errors: CPD_E_INVALID, CPD_E_OOM (ws too small), CPD_E_RANK_DEFICIENT
+ * (leverage), CPD_E_HIP.
  */
-CPD_API cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, double* out);
+CPD_API cpd_status cpd_variance_workspace_size(cpd_handle* h, int32_t n, size_t* bytes);
+CPD_API cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, void* ws, size_t ws_bytes,
+                                double* out);
 
 /* Release the handle (the workspace stays the caller's). */
 CPD_API cpd_status cpd_destroy(cpd_handle* h);
@@ -356,7 +361,11 @@ typedef struct cpd_server_config {
 typedef struct cpd_request {
   cpd_problem problem;
   cpd_options options;            /* fit_every is ignored (round_steps applies) */
-  const void* X;                  /* dense tensor (layout as cpd_init) */
+  const void* X;                  /* dense tensor (layout as cpd_init).  A device X is
+                                     read at admission on the server's own stream, which
+                                     is not ordered after any stream of the caller: the
+                                     caller completes every write to X (e.g. synchronises
+                                     the stream that produced it) before cpd_submit */
   int32_t x_dtype;                /* CPD_F32 or CPD_F64 */
   int32_t x_space;                /* CPD_HOST or CPD_DEVICE (current device) */
   const float* A0[CPD_MAX_MODES]; /* initial factors, host */

@@ -115,7 +115,9 @@ def lib():
             "cpd_read_state": (st, [H, ctypes.c_void_p, P(ctypes.c_size_t)]),
             "cpd_write_state": (st, [H, ctypes.c_void_p, ctypes.c_size_t]),
             "cpd_destroy": (st, [H]),
-            "cpd_variance": (st, [H, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]),
+            "cpd_variance_workspace_size": (st, [H, ctypes.c_int32, P(ctypes.c_size_t)]),
+            "cpd_variance": (st, [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_size_t, P(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -272,11 +274,19 @@ def cpd_write_state(h, blob):
     return check(lib().cpd_write_state(h, buf, len(blob)), "cpd_write_state")
 
 
-def cpd_variance(h, n, sampler):
+def cpd_variance_workspace_size(h, n):
+    out = ctypes.c_size_t()
+    check(lib().cpd_variance_workspace_size(h, int(n), ctypes.byref(out)),
+          "cpd_variance_workspace_size")
+    return out.value
+
+
+def cpd_variance(h, n, sampler, ws_ptr, ws_bytes):
     """(variance, (1/B) sum of the terms, (1/B) ||grad f||^2) for mode n."""
     out = (ctypes.c_double * 3)()
     s = SAMPLER[sampler] if isinstance(sampler, str) else int(sampler)
-    check(lib().cpd_variance(h, int(n), s, out), "cpd_variance")
+    check(lib().cpd_variance(h, int(n), s, ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes),
+                             out), "cpd_variance")
     return out[0], out[1], out[2]
 
 
@@ -559,8 +569,14 @@ class Decomposition:
         cpd_rescale(self.h)
 
     def variance(self, n, sampler):
-        """Exact variance of the sampled gradient of mode n under ``sampler``."""
-        return cpd_variance(self.h, n, sampler)
+        """Exact variance of the sampled gradient of mode n under ``sampler``
+        (the scratch comes from torch's allocator, kept for later calls)."""
+        need = cpd_variance_workspace_size(self.h, n)
+        if getattr(self, "_var_ws", None) is None or self._var_ws[1] < need:
+            self._var_ws = _workspace(need, self.device)[0], need
+        ws = self._var_ws[0]
+        ptr = (ws.data_ptr() + 255) // 256 * 256
+        return cpd_variance(self.h, n, sampler, ptr, need)
 
     def state(self):
         return cpd_read_state(self.h)
@@ -608,6 +624,9 @@ class Server:
             x_ptr, x_space = X.data_ptr(), CPD_DEVICE
             x_dtype = CPD_F64 if X.dtype == torch.float64 else CPD_F32
             Xk = X
+            # admission reads X on the server's own stream: the work that
+            # writes X on the caller's stream must be complete first
+            torch.cuda.current_stream(X.device).synchronize()
         else:
             Xk, x_dtype = _host_tensor(X)
             dims = list(Xk.shape)

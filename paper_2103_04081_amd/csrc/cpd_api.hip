@@ -858,8 +858,19 @@ cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes) {
   return device_status(h);
 }
 
-cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, double* out) {
-  if (!h || !out || n < 0 || n >= h->p.N || sampler < 0 || sampler > 2) {
+cpd_status cpd_variance_workspace_size(cpd_handle* h, int32_t n, size_t* bytes) {
+  if (!h || !bytes || n < 0 || n >= h->p.N) {
+    set_error("bad argument");
+    return CPD_E_INVALID;
+  }
+  *bytes = variance_scratch_bytes(h->desc, n);
+  return CPD_OK;
+}
+
+cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, void* ws, size_t ws_bytes,
+                        double* out) {
+  if (!h || !out || !ws || n < 0 || n >= h->p.N || sampler < 0 || sampler > 2 ||
+      ((uintptr_t)ws & (kAlign - 1))) {
     set_error("bad argument");
     return CPD_E_INVALID;
   }
@@ -869,7 +880,8 @@ cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, double* out) 
   if (s != CPD_OK) return s;
   // the sampler's CDFs are rebuilt one block per mode where that kernel's
   // LDS plan fits (always on the grid path)
-  return variance_eval(h->desc, h->plan.lds, h->plan.refresh_lds, n, sampler, h->stream, out);
+  return variance_eval(h->desc, h->plan.lds, h->plan.refresh_lds, n, sampler, h->stream, out, ws,
+                       ws_bytes);
 }
 
 cpd_status cpd_destroy(cpd_handle* h) {

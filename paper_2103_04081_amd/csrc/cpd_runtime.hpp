@@ -83,8 +83,12 @@ void describe_status(cpd_status s);
 // grid_refresh_lds > 0: the distributions are rebuilt by the grid path's
 // refresh kernel (one block per mode, with that LDS) instead of the
 // persistent kernel.
+// The scratch is caller-owned device memory of at least
+// variance_scratch_bytes(host_desc, n) bytes (CPD_E_OOM otherwise).
+size_t variance_scratch_bytes(const ChainDesc& host_desc, int n);
 cpd_status variance_eval(const ChainDesc& host_desc, size_t lds, size_t grid_refresh_lds, int n,
-                         int sampler, hipStream_t stream, double* out3);
+                         int sampler, hipStream_t stream, double* out3, void* scratch,
+                         size_t scratch_bytes);
 
 void set_error(const std::string& msg);
 cpd_status hip_fail(hipError_t e, const char* what);

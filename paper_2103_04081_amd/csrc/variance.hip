@@ -8,7 +8,7 @@
 // per-mode q/Q of the integer CDFs), and grad f = A^(n) (hadamard_{k!=n}
 // A^(k)T A^(k)) - X_(n) Z^(n).
 //
-// One pass over copy n (row j = fibre j) and three small kernels:
+// One pass over copy n (row j = fibre j) and two small kernels:
 //   variance_pass_kernel<RT>  blocks of 16-row tiles of a row range and a
 //                             group of 16-column tiles: the KRP rows z_j of
 //                             the tile (LDS), then per column tile on the
@@ -17,14 +17,19 @@
 //                             minus x_j, squared and summed per row, and the
 //                             block's part of M = X_(n) Z^(n) (Z^T as the A
 //                             operand, the same fibre values as the B
-//                             operand); per-row sums of squares per column
-//                             group and ||z_j||^2 / p_j go to scratch;
+//                             operand).  The row sums of the group's columns
+//                             times ||z_j||^2 / p_j are summed over the
+//                             block's rows into one FP64 term per block (the
+//                             sum over column groups distributes over the
+//                             product), so nothing of size J is stored;
 //   variance_msum_kernel      M: the block parts summed in a fixed order
 //                             (FP64);
-//   variance_terms_kernel     sum_j ||r_j||^2 ||z_j||^2 / p_j per block of
-//                             rows (FP64);
-//   variance_final_kernel     the terms summed in a fixed order, the Gram
-//                             Hadamard product, grad f and the variance.
+//   variance_final_kernel     the block terms summed in a fixed order, the
+//                             Gram Hadamard product, grad f and the variance.
+//
+// Scratch (caller-owned, or the library's static array for the variant that
+// allocates nothing): the descriptor copy, a state, the sampler's CDFs, the
+// blocks' FP32 parts of M, M in FP64, the block terms and the result.
 #include <cstring>
 #include <string>
 
@@ -42,21 +47,23 @@ __host__ __device__ constexpr int var_tiles_per_wave(int rt) { return rt == 1 ? 
 
 // LDS of a pass block: A^(n) rows of the group's columns (ranks padded to
 // 16 RT), two Z tiles (16 rows, stride 16 RT + 1) and the row multi-indices
-// of two tiles (the current one and the next), the per-wave row sums.
+// of two tiles (the current one and the next), the per-wave row sums and the
+// rows' ||z_j||^2 / p_j.
 __host__ __device__ inline size_t var_pass_lds(int tpg, int RT) {
   return sizeof(float) * (size_t)tpg * 16 * 16 * RT + 2 * sizeof(float) * 16 * (16 * RT + 1) +
-         2 * sizeof(int32_t) * 16 * kMaxModes + sizeof(double) * 4 * 16;
+         2 * sizeof(int32_t) * 16 * kMaxModes + sizeof(double) * 5 * 16;
 }
 
 // Block (c, g): rows [c rpc, (c + 1) rpc) in 16-row tiles, column tiles
 // [g tpg, (g + 1) tpg); wave w takes column tiles g tpg + w, + 4, ...
-//   rr[g][j]      sum over the group's columns of (A^(n) z_j - x_j)^2 (FP64)
-//   zw[j]         ||z_j||^2 / p_j (group 0)
-//   part[c][i][r] sum over the block's rows of x_j(i) z_j(r)
+//   terms[c * ngroups + g]  sum over the block's rows j of
+//                           (sum over the group's columns of (A^(n) z_j - x_j)^2)
+//                           * ||z_j||^2 / p_j   (FP64)
+//   part[c][i][r]           sum over the block's rows of x_j(i) z_j(r)
 template <int RT>
 __global__ void __launch_bounds__(kVpThreads) variance_pass_kernel(
     const ChainDesc* __restrict__ dp, int n, int64_t rpc, int tpg, float* __restrict__ part,
-    double* __restrict__ rr, double* __restrict__ zw) {
+    double* __restrict__ terms) {
   extern __shared__ __align__(16) unsigned char vsm[];
   constexpr int Rp = 16 * RT, ZS = Rp + 1, MT = var_tiles_per_wave(RT);
   const int In = dp->dims[n], R = dp->R, N = dp->N;
@@ -72,7 +79,9 @@ __global__ void __launch_bounds__(kVpThreads) variance_pass_kernel(
   float* As = (float*)vsm;                                // [tpg * 16][Rp]
   float* Zb = As + (size_t)tpg * 16 * Rp;                 // [2][16][ZS]
   int32_t* ikb = (int32_t*)(Zb + 2 * 16 * ZS);            // [2][16][kMaxModes]
-  double* red = (double*)(vsm + var_pass_lds(tpg, RT) - sizeof(double) * 4 * 16);  // [4][16]
+  double* red = (double*)(vsm + var_pass_lds(tpg, RT) - sizeof(double) * 5 * 16);  // [4][16]
+  double* zwl = red + 4 * 16;                             // ||z_j||^2 / p_j of the tile's rows
+  double tacc = 0.0;                                      // threads 0..15: their rows' terms
   const CPD_GLOBAL float* An = gmem((const float*)dp->A[n]);
   for (int e = tid; e < tpg * 16 * Rp; e += kVpThreads) {
     const int i = ct0 * 16 + e / Rp, r = e % Rp;
@@ -171,19 +180,23 @@ __global__ void __launch_bounds__(kVpThreads) variance_pass_kernel(
     }
     float zn[ZE];
     z_tile(t0 + 16, cur ^ 1, zn);
-    if (g == 0 && tid < 16 && t0 + tid < r1) {
+    if (tid < 16) {
       // p_j: product over k != n of q / Q of the sampler's integer CDFs
-      double p = 1.0;
-      for (int k = 0; k < N; ++k) {
-        if (k == n) continue;
-        const CPD_GLOBAL double* C = gmem((const double*)dp->C[k]);
-        const int i = ikb[(cur * 16 + tid) * kMaxModes + k];
-        const double Q = C[dp->dims[k] - 1];
-        p = p * ((C[i] - (i ? C[i - 1] : 0.0)) / Q);
+      double zwv = 0.0;
+      if (t0 + tid < r1) {
+        double p = 1.0;
+        for (int k = 0; k < N; ++k) {
+          if (k == n) continue;
+          const CPD_GLOBAL double* C = gmem((const double*)dp->C[k]);
+          const int i = ikb[(cur * 16 + tid) * kMaxModes + k];
+          const double Q = C[dp->dims[k] - 1];
+          p = p * ((C[i] - (i ? C[i - 1] : 0.0)) / Q);
+        }
+        float z2 = 0.f;
+        for (int r = 0; r < Rp; ++r) z2 = fmaf(Zt[tid * ZS + r], Zt[tid * ZS + r], z2);
+        zwv = p > 0.0 ? (double)z2 / p : 0.0;
       }
-      float z2 = 0.f;
-      for (int r = 0; r < Rp; ++r) z2 = fmaf(Zt[tid * ZS + r], Zt[tid * ZS + r], z2);
-      zw[t0 + tid] = p > 0.0 ? (double)z2 / p : 0.0;
+      zwl[tid] = zwv;
     }
     double r2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -227,8 +240,16 @@ __global__ void __launch_bounds__(kVpThreads) variance_pass_kernel(
     }
     __syncthreads();
     if (tid < 16 && t0 + tid < r1)
-      rr[(int64_t)g * J + t0 + tid] = red[tid] + red[16 + tid] + red[32 + tid] + red[48 + tid];
+      tacc += (red[tid] + red[16 + tid] + red[32 + tid] + red[48 + tid]) * zwl[tid];
     __syncthreads();
+  }
+  // the block's term: the 16 row-slot sums in order
+  if (tid < 16) red[tid] = tacc;
+  __syncthreads();
+  if (tid == 0) {
+    double tsum = 0.0;
+    for (int q = 0; q < 16; ++q) tsum += red[q];
+    terms[(int64_t)c * gridDim.y + g] = tsum;
   }
   // the block's part of M: macc[m][rt][q] = M^T(rank 16 rt + 4 gl + q, column ct * 16 + cl)
   float* out = part + (int64_t)c * In * R;
@@ -267,28 +288,6 @@ __global__ void __launch_bounds__(1024) variance_msum_kernel(const float* __rest
     for (int q = 0; q < 64; ++q) m += red[q][threadIdx.x];
     M[blockIdx.x * 16 + threadIdx.x] = m;
   }
-}
-
-// terms[b] = sum over rows [b rpb, (b + 1) rpb) of (sum_g rr[g][j]) zw[j].
-__global__ void __launch_bounds__(256) variance_terms_kernel(const double* __restrict__ rr,
-                                                             const double* __restrict__ zw,
-                                                             int64_t J, int ngroups,
-                                                             int64_t rpb,
-                                                             double* __restrict__ terms) {
-  __shared__ double red[4];
-  const int64_t j0 = (int64_t)blockIdx.x * rpb;
-  const int64_t j1 = j0 + rpb < J ? j0 + rpb : J;
-  double t = 0.0;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
-    double r = 0.0;
-    for (int g = 0; g < ngroups; ++g) r += rr[(int64_t)g * J + j];
-    t += r * zw[j];
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
-  __syncthreads();
-  if (threadIdx.x == 0) terms[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // out[0] = variance, out[1] = (1/B) sum of the terms, out[2] = ||grad f||^2 / B.
@@ -380,11 +379,18 @@ __global__ void __launch_bounds__(1024) variance_final_kernel(const ChainDesc* _
 
 // Scratch layout and launch shape of one variance evaluation.
 struct VarPlan {
-  int ngroups, tpg, nchunks, nblocks;
-  int64_t J, rpc, rpb;
+  int ngroups, tpg, nchunks;
+  int64_t J, rpc;
   size_t lds;
-  size_t desc, state, cdf, part, rr, zw, M, terms, out, total;
+  size_t desc, state, cdf, part, M, terms, out, total;
 };
+
+// Bytes of the blocks' FP32 parts of M, at most: the number of row chunks
+// is capped so that nchunks * I_n * R * 4 stays within this.
+constexpr size_t kVarPartBudget = 16u << 20;
+// Row chunks of the pass planned by variance_scratch_bytes: at least as many
+// pass blocks as any MI355X holds at once (256 CUs x 4 blocks).
+constexpr int kVarMaxBlocks = 1024;
 
 // target_blocks: pass blocks the GPU holds at once (one round of blocks
 // measured fastest: 66 vs 90 us at 300^3 against 1.2 rounds).
@@ -401,14 +407,13 @@ static VarPlan plan_variance(const ChainDesc& d, int n, int target_blocks) {
   v.lds = var_pass_lds(v.tpg, RT);
   // one round of resident blocks, rows in whole 16-row tiles
   int64_t nch = (target_blocks + v.ngroups - 1) / v.ngroups;
+  const int64_t cap = (int64_t)(kVarPartBudget / ((size_t)d.dims[n] * d.R * sizeof(float)));
+  if (nch > cap) nch = cap;
   if (nch < 1) nch = 1;
   const int64_t tiles = (v.J + 15) / 16;
   if (nch > tiles) nch = tiles;
   v.rpc = (tiles + nch - 1) / nch * 16;
   v.nchunks = (int)((v.J + v.rpc - 1) / v.rpc);
-  int64_t nb = (v.J + 1023) / 1024;
-  v.nblocks = (int)(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
-  v.rpb = (v.J + v.nblocks - 1) / v.nblocks;
   size_t off = 0;
   auto take = [&](size_t b) {
     const size_t o = off;
@@ -421,10 +426,8 @@ static VarPlan plan_variance(const ChainDesc& d, int n, int target_blocks) {
   v.state = take(sizeof(ChainState) + 64);
   v.cdf = take(sizeof(double) * sumdims);
   v.part = take(sizeof(float) * (size_t)v.nchunks * d.dims[n] * d.R);
-  v.rr = take(sizeof(double) * (size_t)v.ngroups * v.J);
-  v.zw = take(sizeof(double) * (size_t)v.J);
   v.M = take(sizeof(double) * (size_t)d.dims[n] * d.R);
-  v.terms = take(sizeof(double) * v.nblocks);
+  v.terms = take(sizeof(double) * (size_t)v.nchunks * v.ngroups);
   v.out = take(sizeof(double) * 4);
   v.total = off;
   return v;
@@ -438,7 +441,7 @@ static hipError_t launch_pass(const VarPlan& v, const ChainDesc* dd, int n, char
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((variance_pass_kernel<RT>), dim3(v.nchunks, v.ngroups), dim3(kVpThreads),
                      v.lds, stream, dd, n, v.rpc, v.tpg, (float*)(scratch + v.part),
-                     (double*)(scratch + v.rr), (double*)(scratch + v.zw));
+                     (double*)(scratch + v.terms));
   return hipGetLastError();
 }
 
@@ -455,8 +458,13 @@ static int pass_capacity(size_t lds) {
   return cus * per_cu;
 }
 
+size_t variance_scratch_bytes(const ChainDesc& hd, int n) {
+  return plan_variance(hd, n, kVarMaxBlocks).total;
+}
+
 cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_lds, int n,
-                         int sampler, hipStream_t stream, double* out3) {
+                         int sampler, hipStream_t stream, double* out3, void* scratch_v,
+                         size_t scratch_bytes) {
   VarPlan v = plan_variance(hd, n, 768);
   int cap = 768;
   switch (hd.RT) {
@@ -465,17 +473,13 @@ cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_ld
     case 3: cap = pass_capacity<3>(v.lds); break;
     default: cap = pass_capacity<4>(v.lds); break;
   }
-  v = plan_variance(hd, n, cap);
-  char* scratch = nullptr;
-  hipError_t e = hipMalloc((void**)&scratch, v.total);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(variance scratch)");
-  auto done = [&](cpd_status s) {
-    (void)hipStreamSynchronize(stream);
-    (void)hipFree(scratch);
-    return s;
-  };
-  e = hipMemsetAsync(scratch, 0, v.total, stream);
-  if (e != hipSuccess) return done(hip_fail(e, "hipMemsetAsync"));
+  v = plan_variance(hd, n, cap < kVarMaxBlocks ? cap : kVarMaxBlocks);
+  if (!scratch_v || v.total > scratch_bytes) {
+    set_error("variance scratch of " + std::to_string(scratch_bytes) + " bytes; this mode needs " +
+              std::to_string(v.total));
+    return CPD_E_OOM;
+  }
+  char* scratch = (char*)scratch_v;
   // the requested sampler's distributions of the current factors
   ChainDesc d = hd;
   d.sampler = sampler;
@@ -488,8 +492,14 @@ cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_ld
   d.active = 1;
   d.autostop = 0;
   ChainDesc* dd = (ChainDesc*)(scratch + v.desc);
-  e = hipMemcpyAsync(dd, &d, sizeof d, hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) return done(hip_fail(e, "hipMemcpyAsync(desc)"));
+  // the state starts at zero (status, clock); every other region is
+  // written in full before it is read
+  const ChainState zero_state{};
+  hipError_t e = hipMemcpyAsync(dd, &d, sizeof d, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(scratch + v.state, &zero_state, sizeof zero_state, hipMemcpyHostToDevice,
+                       stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(desc)");
   if (grid_refresh_lds > 0) {
     e = launch_wide_refresh(dd, d.RT, grid_refresh_lds, nullptr, -1, d.N, stream);
   } else {
@@ -497,36 +507,33 @@ cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_ld
     a.op = OP_REFRESH;
     e = launch_chain_kernel(dd, 1, d.RT, lds, a, stream);
   }
-  if (e != hipSuccess) return done(hip_fail(e, "refresh kernel"));
+  if (e != hipSuccess) return hip_fail(e, "refresh kernel");
   switch (d.RT) {
     case 1: e = launch_pass<1>(v, dd, n, scratch, stream); break;
     case 2: e = launch_pass<2>(v, dd, n, scratch, stream); break;
     case 3: e = launch_pass<3>(v, dd, n, scratch, stream); break;
     default: e = launch_pass<4>(v, dd, n, scratch, stream); break;
   }
-  if (e != hipSuccess) return done(hip_fail(e, "variance pass kernel"));
+  if (e != hipSuccess) return hip_fail(e, "variance pass kernel");
   const int E = d.dims[n] * d.R;
   hipLaunchKernelGGL(variance_msum_kernel, dim3((E + 15) / 16), dim3(1024), 0, stream,
                      (const float*)(scratch + v.part), v.nchunks, E, (double*)(scratch + v.M));
-  hipLaunchKernelGGL(variance_terms_kernel, dim3(v.nblocks), dim3(256), 0, stream,
-                     (const double*)(scratch + v.rr), (const double*)(scratch + v.zw), v.J,
-                     v.ngroups, v.rpb, (double*)(scratch + v.terms));
   hipLaunchKernelGGL(variance_final_kernel, dim3(1), dim3(1024), 0, stream, dd, n,
-                     (const double*)(scratch + v.M), v.nblocks,
+                     (const double*)(scratch + v.M), v.nchunks * v.ngroups,
                      (const double*)(scratch + v.terms), (double*)(scratch + v.out));
   e = hipGetLastError();
-  if (e != hipSuccess) return done(hip_fail(e, "variance kernels"));
+  if (e != hipSuccess) return hip_fail(e, "variance kernels");
   ChainState st;
   e = hipMemcpyAsync(&st, scratch + v.state, sizeof st, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out3, scratch + v.out, sizeof(double) * 3, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) return done(hip_fail(e, "variance result"));
+  if (e != hipSuccess) return hip_fail(e, "variance result");
   if (st.status != 0) {
     describe_status(st.status);
-    return done(st.status);
+    return st.status;
   }
-  return done(CPD_OK);
+  return CPD_OK;
 }
 
 }  // namespace cpdmi
