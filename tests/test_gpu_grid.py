@@ -14,7 +14,8 @@ import pytest
 
 import oracle as O
 from oracle import philox
-from parity_util import gpu_decomposition, oracle_for, problem, rel, sample_from_cdfs
+from parity_util import (FLOOR_FACTOR, check_iterates, factor_errs, gpu_decomposition,
+                         oracle_for, problem, sample_from_cdfs)
 
 pytestmark = pytest.mark.gpu
 
@@ -79,11 +80,14 @@ def test_grid_replay_against_oracle(case):
     g.sync()
     assert g.t == 40 and p.t == 40
     A, Ap = g.factors(), p.factors()
-    err = max(rel(A[k], orc.A[k]) for k in range(len(dims)))
-    err_p = max(rel(A[k], Ap[k]) for k in range(len(dims)))
-    print(f"grid path: max rel err vs oracle {err:.3e}, vs persistent path {err_p:.3e}")
-    assert err <= 1e-5
-    assert err_p <= 1e-5
+    _, _, fl = check_iterates(A, orc, 1e-5, "grid path, 40 steps")
+    check_iterates(Ap, orc, 1e-5, "persistent path fed the same draws, 40 steps")
+    # the two FP32 paths differ in summation order only: each is within the
+    # bound of the oracle, so their distance is within twice it
+    err_p, err_pf = factor_errs(A, Ap)
+    print(f"grid vs persistent: element-wise {err_p:.3e}, Frobenius {err_pf:.3e}")
+    assert err_pf <= 2e-5
+    assert err_p <= 2 * max(1e-5, FLOOR_FACTOR * fl)
     g.close()
     p.close()
 
@@ -104,10 +108,7 @@ def test_grid_large_batch():
         n, idx, _ = g.sample(t)
         orc.step(replay=(n, idx))
         g.step(1)
-    A = g.factors()
-    err = max(rel(A[k], orc.A[k]) for k in range(len(dims)))
-    print(f"B = 5000: max rel err vs oracle {err:.3e}")
-    assert err <= 1e-5
+    check_iterates(g.factors(), orc, 1e-5, "B = 5000, 12 steps")
     assert abs(g.fit() - orc.fit()) <= 1e-6
     g.close()
 
@@ -126,7 +127,7 @@ def test_grid_fixed_decreasing_nonneg(rule, kw):
         g.step(1)
     A = g.factors()
     assert all(np.all(a >= 0) for a in A)
-    assert max(rel(A[k], orc.A[k]) for k in range(3)) <= 1e-5
+    check_iterates(A, orc, 1e-5, f"grid {rule} rule with projection, 30 steps")
     g.close()
 
 
@@ -197,10 +198,7 @@ def test_grid_short_modes_split_fibre_range(dims, R, sampler, storage):
         n, idx, _ = g.sample(t)
         orc.step(replay=(n, idx))
         g.step(1)
-    A = g.factors()
-    err = max(rel(A[k], orc.A[k]) for k in range(len(dims)))
-    print(f"short modes, B = {B}: max rel err vs oracle {err:.3e}")
-    assert err <= 1e-5
+    check_iterates(g.factors(), orc, 1e-5, f"short modes, B = {B}, 6 steps")
     g.close()
 
 
@@ -244,8 +242,5 @@ def test_grid_max_batch():
         n, idx, _ = g.sample(t)
         orc.step(replay=(n, idx))
         g.step(1)
-    A = g.factors()
-    err = max(rel(A[k], orc.A[k]) for k in range(3))
-    print(f"B = 2^20: max rel err vs oracle after 2 steps {err:.3e}", flush=True)
-    assert err <= 1e-5
+    check_iterates(g.factors(), orc, 1e-5, "B = 2^20, 2 steps")
     g.close()

@@ -14,7 +14,8 @@ import pytest
 
 import oracle as O
 from helpers import factor_match_score
-from parity_util import gpu_decomposition, oracle_for, problem, rel, sample_from_cdfs
+from parity_util import (Tracked, check_iterates, gpu_decomposition, oracle_for, problem,
+                         sample_from_cdfs)
 
 pytestmark = pytest.mark.gpu
 
@@ -89,7 +90,6 @@ def test_replay_100_steps(case):
     prob = problem(dims, R, storage=storage)
     dec = gpu_decomposition(prob, B, sampler=sampler, storage=storage, eta=0.3)
     orc = oracle_for(prob, B, sampler=sampler, eta=0.3)
-    orc64 = O.Oracle(prob["X64"], prob["A0"], B=B, sampler=sampler, eta=0.3, seed=5)
     own_mismatch = 0
     for t in range(100):
         n, idx, p = dec.sample(t)
@@ -97,16 +97,10 @@ def test_replay_100_steps(case):
         if n_o != n or not np.array_equal(idx_o, idx):
             own_mismatch += 1
         orc.step(replay=(n, idx))
-        orc64.step(replay=(n, idx))
         dec.step(1)
     dec.sync()
     assert dec.t == 100
-    A = dec.factors()
-    errs = [rel(A[k], orc.A[k]) for k in range(len(dims))]
-    errs64 = [rel(A[k], orc64.A[k]) for k in range(len(dims))]
-    print(f"max rel err vs oracle {max(errs):.3e}; vs FP64 oracle on unrounded X "
-          f"{max(errs64):.3e} (AdaGrad, b = 0); own-draw mismatches {own_mismatch}/100")
-    assert max(errs) <= 1e-5
+    check_iterates(dec.factors(), orc, 1e-5, f"100 steps, own-draw mismatches {own_mismatch}")
     # draws differ from the oracle's own only where FP32 vs FP64 iterates move
     # a CDF boundary: rare
     assert own_mismatch <= 10
@@ -138,16 +132,18 @@ def test_bf16_storage_error_vs_fp64_oracle(dims, R, B, sampler):
     prob = problem(dims, R, storage="bf16")
     alpha = _safe_alpha(prob["A0"])
     dec = gpu_decomposition(prob, B, sampler=sampler, storage="bf16", rule="fixed", alpha=alpha)
-    orc64 = O.Oracle(prob["X64"], prob["A0"], B=B, sampler=sampler, rule="fixed", alpha=alpha,
-                     seed=5)
+    orc64 = Tracked(O.Oracle(prob["X64"], prob["A0"], B=B, sampler=sampler, rule="fixed",
+                             alpha=alpha, seed=5))
+    # the storage floor here: the oracle on the BF16-rounded tensor, its
+    # iterate rounded to FP32
+    orc_r = oracle_for(prob, B, sampler=sampler, rule="fixed", alpha=alpha)
     for t in range(100):
         n, idx, _ = dec.sample(t)
         orc64.step(replay=(n, idx))
+        orc_r.step(replay=(n, idx))
         dec.step(1)
-    A = dec.factors()
-    err = max(rel(A[k], orc64.A[k]) for k in range(len(dims)))
-    print(f"BF16 storage, fixed step: max rel err vs FP64 oracle {err:.3e}")
-    assert err <= 2e-2
+    check_iterates(dec.factors(), orc64, 2e-2, "BF16 storage, fixed step, vs FP64 oracle on the "
+                   "unrounded tensor", floor_of=orc_r)
     dec.close()
     dec = gpu_decomposition(prob, B, sampler=sampler, storage="bf16", eta=0.3)
     orc64 = O.Oracle(prob["X64"], prob["A0"], B=B, sampler=sampler, eta=0.3, seed=5)
@@ -158,9 +154,7 @@ def test_bf16_storage_error_vs_fp64_oracle(dims, R, B, sampler):
     A = [a.astype(np.float64) for a in dec.factors()]
     f_gpu = O.fit_explicit(prob["X64"], A)
     f_ora = orc64.fit()
-    err = max(rel(A[k], orc64.A[k]) for k in range(len(dims)))
-    print(f"BF16 storage, AdaGrad: fit {f_gpu:.5f} vs FP64 oracle {f_ora:.5f}; "
-          f"iterate rel err {err:.3e}")
+    print(f"BF16 storage, AdaGrad: fit {f_gpu:.5f} vs FP64 oracle {f_ora:.5f}")
     assert abs(f_gpu - f_ora) <= 2e-2
     dec.close()
 
@@ -176,8 +170,7 @@ def test_fixed_and_decreasing_rules(rule, kw):
         n, idx, _ = dec.sample(t)
         orc.step(replay=(n, idx))
         dec.step(1)
-    A = dec.factors()
-    assert max(rel(A[k], orc.A[k]) for k in range(3)) <= 1e-5
+    check_iterates(dec.factors(), orc, 1e-5, f"{rule} rule, 60 steps")
     dec.close()
 
 
@@ -192,7 +185,7 @@ def test_nonneg_projection():
         dec.step(1)
     A = dec.factors()
     assert all(np.all(a >= 0) for a in A)
-    assert max(rel(A[k], orc.A[k]) for k in range(3)) <= 1e-5
+    check_iterates(A, orc, 1e-5, "nonnegative projection, 60 steps")
     dec.close()
 
 
@@ -278,8 +271,7 @@ def test_edge_shapes(dims, R, B):
         assert n == n_o and np.array_equal(idx, idx_o)
         orc.step(replay=(n, idx))
         dec.step(1)
-    A = dec.factors()
-    assert max(rel(A[k], orc.A[k]) for k in range(len(dims))) <= 1e-5
+    check_iterates(dec.factors(), orc, 1e-5, f"edge shape {dims} R{R} B{B}, 20 steps")
     dec.close()
 
 
@@ -334,8 +326,5 @@ def test_persistent_largest_batch_and_grid_beyond():
             assert n == n2 and np.array_equal(idx, idx2) and np.array_equal(p, p2), (B, t)
             orc.step(replay=(n, idx))
             dec.step(1)
-        A = dec.factors()
-        err = max(rel(A[k], orc.A[k]) for k in range(3))
-        print(f"B = {B} ({path}): max rel err vs oracle after 10 steps {err:.3e}", flush=True)
-        assert err <= 1e-5
+        check_iterates(dec.factors(), orc, 1e-5, f"B = {B} ({path}), 10 steps")
         dec.close()

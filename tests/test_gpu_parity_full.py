@@ -1,18 +1,19 @@
 """GPU parity at the full workload sizes, in the launch configuration the
 benchmark times (one persistent workgroup per decomposition).
 
-The oracle cannot run these sizes for long, but one step of it only touches
-the sampled fibres, so it replays the device's draws step by step: sampling
-is checked bit for bit (against the oracle's sampler on the device's CDFs)
-and the iterates after a few steps within the FP32 tolerance.  Every member
-of the 64-tensor batch recipe is covered the same way."""
+One step of the oracle only touches the sampled fibres, so it replays the
+device's draws step by step: sampling is checked bit for bit (against the
+oracle's sampler on the device's CDFs, and the device's CDFs against the
+oracle's distribution of the device's own factors) and the iterates after
+100 steps within the FP32 tolerance, element by element.  Every member of
+the 64-tensor batch recipe is covered the same way for a few steps."""
 
 import numpy as np
 import pytest
 
 import cpd_inputs as ci
 import oracle as O
-from parity_util import gpu_decomposition, rel, sample_from_cdfs
+from parity_util import Tracked, check_iterates, gpu_decomposition, sample_from_cdfs
 
 pytestmark = pytest.mark.gpu
 
@@ -20,8 +21,8 @@ pytestmark = pytest.mark.gpu
 def _replay(prob, B, steps, *, sampler, storage, eta, seed, stream_id=0, tol=1e-5, label=""):
     dec = gpu_decomposition(prob, B, sampler=sampler, storage=storage, eta=eta, seed=seed,
                             stream_id=stream_id)
-    orc = O.Oracle(prob["X"], prob["A0"], B=B, sampler=sampler, eta=eta, seed=seed,
-                   stream_id=stream_id)
+    orc = Tracked(O.Oracle(prob["X"], prob["A0"], B=B, sampler=sampler, eta=eta, seed=seed,
+                           stream_id=stream_id))
     N = len(prob["dims"])
     for t in range(steps):
         cdfs = [dec.cdf(n) for n in range(N)]
@@ -37,29 +38,33 @@ def _replay(prob, B, steps, *, sampler, storage, eta, seed, stream_id=0, tol=1e-
                 assert np.array_equal(cdfs[k], C_ref), (label, t, k)
         orc.step(replay=(n, idx))
         dec.step(1)
-    A = dec.factors()
-    err = max(rel(A[k], orc.A[k]) for k in range(N))
-    print(f"{label}: {steps} steps, max rel err vs oracle {err:.3e}", flush=True)
-    assert err <= tol, label
+    err, err_f, _ = check_iterates(dec.factors(), orc, tol, f"{label}: {steps} steps")
     dec.close()
-    return err
+    return err_f
 
 
+# AdaGrad eta of the 100-step replays: 0.5 (300^3) and 0.3 (120^4).  At the
+# benchmark's eta = 5 the first steps are sign steps of size 5 on entries of
+# order one; the trajectory is then so sensitive that an FP64 oracle whose
+# factors are merely rounded to FP32 after each update departs from the
+# unrounded one by 3e-6 to 1e-5 norm-wise within 100 steps (eta = 3), which
+# leaves no room to tell a defect from rounding.  The kernels and launch
+# shapes are the benchmark's; only the step size differs.
 def test_full_300cube_f32():
     w = ci.workload(2)
-    _replay(w, w["B"], 20, sampler="euclidean", storage="f32", eta=3.0, seed=w["seed"],
+    _replay(w, w["B"], 100, sampler="euclidean", storage="f32", eta=0.5, seed=w["seed"],
             label="300^3 R10 B256 f32")
 
 
 def test_full_300cube_leverage():
     w = ci.workload(2)
-    _replay(w, w["B"], 10, sampler="leverage", storage="f32", eta=3.0, seed=w["seed"],
+    _replay(w, w["B"], 100, sampler="leverage", storage="f32", eta=0.5, seed=w["seed"],
             label="300^3 R10 B256 leverage")
 
 
 def test_full_120_4way_bf16():
     w = ci.workload(3, dtype="bf16")
-    _replay(w, w["B"], 12, sampler="euclidean", storage="bf16", eta=1.5, seed=w["seed"],
+    _replay(w, w["B"], 100, sampler="euclidean", storage="bf16", eta=0.3, seed=w["seed"],
             label="120^4 R20 B512 bf16")
 
 
@@ -136,23 +141,30 @@ def test_full_120_4way_storage_error_vs_fp64_oracle():
                 V = V * (A.T @ A)
         lam = max(lam, float(np.linalg.eigvalsh(V)[-1]))
     alpha = 0.1 / lam
-    errs = {}
+    errs, errs_f = {}, {}
     for storage in ("f32", "bf16"):
         dec = gpu_decomposition(w32, w32["B"], sampler="euclidean", storage=storage, rule="fixed",
                                 alpha=alpha, seed=w32["seed"])
-        orc64 = O.Oracle(w32["X64"], w32["A0"], B=w32["B"], sampler="euclidean", rule="fixed",
-                         alpha=alpha, seed=w32["seed"])
-        for t in range(12):
+        orc64 = Tracked(O.Oracle(w32["X64"], w32["A0"], B=w32["B"], sampler="euclidean",
+                                 rule="fixed", alpha=alpha, seed=w32["seed"]))
+        # the storage floor: the oracle on the stored tensor (FP32 or BF16
+        # rounded), its iterate rounded to FP32
+        Xs = w32["X"] if storage == "f32" else ci.round_bf16(w32["X"])
+        orc_r = Tracked(O.Oracle(Xs, w32["A0"], B=w32["B"], sampler="euclidean", rule="fixed",
+                                 alpha=alpha, seed=w32["seed"]))
+        for t in range(100):
             n, idx, _ = dec.sample(t)
             orc64.step(replay=(n, idx))
+            orc_r.step(replay=(n, idx))
             dec.step(1)
-        A = dec.factors()
-        errs[storage] = max(rel(A[k], orc64.A[k]) for k in range(4))
+        errs[storage], errs_f[storage], _ = check_iterates(
+            dec.factors(), orc64, 1e-5 if storage == "f32" else 2e-2,
+            f"120^4 {storage} storage vs FP64 oracle on the unrounded tensor", floor_of=orc_r)
+        del orc_r, Xs
         dec.close()
-    print(f"120^4 R20 B512, 12 steps, fixed step: error vs FP64 oracle on the unrounded tensor: "
-          f"FP32 storage {errs['f32']:.3e}, BF16 storage {errs['bf16']:.3e}", flush=True)
-    assert errs["f32"] <= 1e-5
-    assert errs["bf16"] <= 2e-2
+    print(f"120^4 R20 B512, 100 steps, fixed step: error vs FP64 oracle on the unrounded tensor, "
+          f"element-wise (Frobenius): FP32 storage {errs['f32']:.3e} ({errs_f['f32']:.3e}), "
+          f"BF16 storage {errs['bf16']:.3e} ({errs_f['bf16']:.3e})", flush=True)
 
 
 @pytest.mark.parametrize("which,B,storage", [(2, 65536, "f32"), (3, 65536, "bf16")])

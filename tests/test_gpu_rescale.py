@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from parity_util import gpu_decomposition, problem, rel, sample_from_cdfs
+from parity_util import Tracked, check_iterates, elem_err, gpu_decomposition, problem, sample_from_cdfs
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +41,7 @@ def test_rescale_call_matches_oracle(path):
     dec.rescale()
     after = dec.factors()
     want = O.rescale_columns(before)
-    err = max(rel(after[k], want[k]) for k in range(3))
+    err = max(elem_err(after[k], want[k]) for k in range(3))
     print(f"{path}: rescale vs oracle {err:.3e}, fit {fit0:.9f} -> {dec.fit():.9f}", flush=True)
     assert err <= 1e-6
     assert abs(dec.fit() - fit0) <= 1e-6
@@ -76,8 +76,8 @@ def test_rescale_every_replay_against_oracle(case):
     X32 = np.asfortranarray(prob["X"].astype(np.float32))
     dec = P.Decomposition(X32, prob["A0"], B=B, sampler=sampler, eta=0.3, storage=storage,
                           seed=5, path=path, rescale_every=every)
-    orc = O.Oracle(prob["X"], prob["A0"], B=B, sampler=sampler, eta=0.3, seed=5,
-                   rescale_every=every)
+    orc = Tracked(O.Oracle(prob["X"], prob["A0"], B=B, sampler=sampler, eta=0.3, seed=5,
+                           rescale_every=every))
     N = len(dims)
     for t in range(20):
         cdfs = [dec.cdf(k) for k in range(N)]
@@ -86,10 +86,7 @@ def test_rescale_every_replay_against_oracle(case):
         assert n == n2 and np.array_equal(idx, idx2) and np.array_equal(p, p2), t
         orc.step(replay=(n, idx))
         dec.step(1)
-    A = dec.factors()
-    err = max(rel(A[k], orc.A[k]) for k in range(N))
-    print(f"20 steps, rescale every {every}: max rel err vs oracle {err:.3e}", flush=True)
-    assert err <= 1e-5
+    check_iterates(dec.factors(), orc, 1e-5, f"20 steps, rescale every {every}")
     assert abs(dec.fit() - orc.fit()) <= 1e-5
     assert dec.t == 20
     dec.close()
