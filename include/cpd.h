@@ -254,6 +254,21 @@ CPD_API cpd_status cpd_variance_workspace_size(cpd_handle* h, int32_t n, size_t*
 CPD_API cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, void* ws, size_t ws_bytes,
                                 double* out);
 
+/*
+ * cpd_variance_noalloc: cpd_variance without a scratch argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid allocation).  It allocates nothing: its
+ * scratch is one static array of the library per device (20 MiB, held from
+ * the first call on that device until the process ends), which covers every
+ * problem within this header's limits (the request is refused with
+ * CPD_E_INVALID if a mode's scratch ever exceeded it).  Results are those of
+ * cpd_variance bit for bit.  All calls on one device share that array, which
+ * keeps the last call's contents: calls that overlap on one device (from
+ * different threads or streams) race and must be serialised by the caller.
+ * Synchronous on the handle's stream.  Errors as cpd_variance.
+ */
+CPD_API cpd_status cpd_variance_noalloc(cpd_handle* h, int32_t n, int32_t sampler, double* out);
+
 /* Release the handle (the workspace stays the caller's). */
 CPD_API cpd_status cpd_destroy(cpd_handle* h);
 

@@ -118,6 +118,7 @@ def lib():
             "cpd_variance_workspace_size": (st, [H, ctypes.c_int32, P(ctypes.c_size_t)]),
             "cpd_variance": (st, [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_size_t, P(ctypes.c_double)]),
+            "cpd_variance_noalloc": (st, [H, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -287,6 +288,14 @@ def cpd_variance(h, n, sampler, ws_ptr, ws_bytes):
     s = SAMPLER[sampler] if isinstance(sampler, str) else int(sampler)
     check(lib().cpd_variance(h, int(n), s, ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes),
                              out), "cpd_variance")
+    return out[0], out[1], out[2]
+
+
+def cpd_variance_noalloc(h, n, sampler):
+    """cpd_variance with the library's static scratch (allocates nothing)."""
+    out = (ctypes.c_double * 3)()
+    s = SAMPLER[sampler] if isinstance(sampler, str) else int(sampler)
+    check(lib().cpd_variance_noalloc(h, int(n), s, out), "cpd_variance_noalloc")
     return out[0], out[1], out[2]
 
 

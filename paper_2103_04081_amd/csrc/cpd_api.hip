@@ -884,6 +884,28 @@ cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, void* ws, siz
                        ws_bytes);
 }
 
+cpd_status cpd_variance_noalloc(cpd_handle* h, int32_t n, int32_t sampler, double* out) {
+  if (!h || !out || n < 0 || n >= h->p.N || sampler < 0 || sampler > 2) {
+    set_error("bad argument");
+    return CPD_E_INVALID;
+  }
+  cpd_status s = set_device(h);
+  if (s != CPD_OK) return s;
+  s = device_status(h);
+  if (s != CPD_OK) return s;
+  const size_t need = variance_scratch_bytes(h->desc, n);
+  if (need > kVarStaticScratch) {
+    set_error("cpd_variance_noalloc: this mode needs " + std::to_string(need) +
+              " bytes of scratch, above the static " + std::to_string(kVarStaticScratch));
+    return CPD_E_INVALID;
+  }
+  void* ws = nullptr;
+  s = variance_static_scratch(&ws);
+  if (s != CPD_OK) return s;
+  return variance_eval(h->desc, h->plan.lds, h->plan.refresh_lds, n, sampler, h->stream, out, ws,
+                       kVarStaticScratch);
+}
+
 cpd_status cpd_destroy(cpd_handle* h) {
   if (!h) return CPD_OK;
   (void)hipSetDevice(h->device);

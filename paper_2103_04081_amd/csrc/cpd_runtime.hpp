@@ -86,6 +86,10 @@ void describe_status(cpd_status s);
 // The scratch is caller-owned device memory of at least
 // variance_scratch_bytes(host_desc, n) bytes (CPD_E_OOM otherwise).
 size_t variance_scratch_bytes(const ChainDesc& host_desc, int n);
+// Bytes of the static scratch of cpd_variance_noalloc (one array per device),
+// and its device address on the current device (looked up once per device).
+constexpr size_t kVarStaticScratch = 20u << 20;
+cpd_status variance_static_scratch(void** ptr);
 cpd_status variance_eval(const ChainDesc& host_desc, size_t lds, size_t grid_refresh_lds, int n,
                          int sampler, hipStream_t stream, double* out3, void* scratch,
                          size_t scratch_bytes);

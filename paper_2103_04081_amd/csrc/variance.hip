@@ -31,6 +31,7 @@
 // allocates nothing): the descriptor copy, a state, the sampler's CDFs, the
 // blocks' FP32 parts of M, M in FP64, the block terms and the result.
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "cpd_runtime.hpp"
@@ -434,14 +435,14 @@ static VarPlan plan_variance(const ChainDesc& d, int n, int target_blocks) {
 }
 
 template <int RT>
-static hipError_t launch_pass(const VarPlan& v, const ChainDesc* dd, int n, char* scratch,
+static hipError_t launch_pass(const VarPlan& v, const ChainDesc* dd, int n, char* base,
                               hipStream_t stream) {
   static std::atomic<uint32_t> attr{0};
   hipError_t e = set_lds_limit_once((const void*)variance_pass_kernel<RT>, 160 * 1024, &attr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((variance_pass_kernel<RT>), dim3(v.nchunks, v.ngroups), dim3(kVpThreads),
-                     v.lds, stream, dd, n, v.rpc, v.tpg, (float*)(scratch + v.part),
-                     (double*)(scratch + v.terms));
+                     v.lds, stream, dd, n, v.rpc, v.tpg, (float*)(base + v.part),
+                     (double*)(base + v.terms));
   return hipGetLastError();
 }
 
@@ -462,6 +463,38 @@ size_t variance_scratch_bytes(const ChainDesc& hd, int n) {
   return plan_variance(hd, n, kVarMaxBlocks).total;
 }
 
+// Scratch of the variance evaluation that allocates nothing
+// (cpd_variance_noalloc): one array per device, held until the process
+// ends.  Its size covers every problem within the library's limits: the
+// parts of M are capped at kVarPartBudget, M itself takes at most
+// CPD_MAX_DIM * CPD_MAX_RANK doubles, the CDFs CPD_MAX_MODES * CPD_MAX_DIM
+// doubles, the rest a few KiB.  In host code the array's name is only a
+// host-side stand-in; kernels and copies use the device address returned by
+// hipGetSymbolAddress for the current device.
+static __device__ __align__(256) char scratch[kVarStaticScratch];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];  // per device ordinal; null until looked up
+
+cpd_status variance_static_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) {
+    set_error("device ordinal beyond the static scratch table");
+    return CPD_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(variance scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return CPD_OK;
+}
+
 cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_lds, int n,
                          int sampler, hipStream_t stream, double* out3, void* scratch_v,
                          size_t scratch_bytes) {
@@ -479,25 +512,25 @@ cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_ld
               std::to_string(v.total));
     return CPD_E_OOM;
   }
-  char* scratch = (char*)scratch_v;
+  char* base = (char*)scratch_v;
   // the requested sampler's distributions of the current factors
   ChainDesc d = hd;
   d.sampler = sampler;
   size_t coff = 0;
   for (int k = 0; k < d.N; ++k) {
-    d.C[k] = (double*)(scratch + v.cdf) + coff;
+    d.C[k] = (double*)(base + v.cdf) + coff;
     coff += d.dims[k];
   }
-  d.state = (ChainState*)(scratch + v.state);
+  d.state = (ChainState*)(base + v.state);
   d.active = 1;
   d.autostop = 0;
-  ChainDesc* dd = (ChainDesc*)(scratch + v.desc);
+  ChainDesc* dd = (ChainDesc*)(base + v.desc);
   // the state starts at zero (status, clock); every other region is
   // written in full before it is read
   const ChainState zero_state{};
   hipError_t e = hipMemcpyAsync(dd, &d, sizeof d, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(scratch + v.state, &zero_state, sizeof zero_state, hipMemcpyHostToDevice,
+    e = hipMemcpyAsync(base + v.state, &zero_state, sizeof zero_state, hipMemcpyHostToDevice,
                        stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(desc)");
   if (grid_refresh_lds > 0) {
@@ -509,24 +542,24 @@ cpd_status variance_eval(const ChainDesc& hd, size_t lds, size_t grid_refresh_ld
   }
   if (e != hipSuccess) return hip_fail(e, "refresh kernel");
   switch (d.RT) {
-    case 1: e = launch_pass<1>(v, dd, n, scratch, stream); break;
-    case 2: e = launch_pass<2>(v, dd, n, scratch, stream); break;
-    case 3: e = launch_pass<3>(v, dd, n, scratch, stream); break;
-    default: e = launch_pass<4>(v, dd, n, scratch, stream); break;
+    case 1: e = launch_pass<1>(v, dd, n, base, stream); break;
+    case 2: e = launch_pass<2>(v, dd, n, base, stream); break;
+    case 3: e = launch_pass<3>(v, dd, n, base, stream); break;
+    default: e = launch_pass<4>(v, dd, n, base, stream); break;
   }
   if (e != hipSuccess) return hip_fail(e, "variance pass kernel");
   const int E = d.dims[n] * d.R;
   hipLaunchKernelGGL(variance_msum_kernel, dim3((E + 15) / 16), dim3(1024), 0, stream,
-                     (const float*)(scratch + v.part), v.nchunks, E, (double*)(scratch + v.M));
+                     (const float*)(base + v.part), v.nchunks, E, (double*)(base + v.M));
   hipLaunchKernelGGL(variance_final_kernel, dim3(1), dim3(1024), 0, stream, dd, n,
-                     (const double*)(scratch + v.M), v.nchunks * v.ngroups,
-                     (const double*)(scratch + v.terms), (double*)(scratch + v.out));
+                     (const double*)(base + v.M), v.nchunks * v.ngroups,
+                     (const double*)(base + v.terms), (double*)(base + v.out));
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "variance kernels");
   ChainState st;
-  e = hipMemcpyAsync(&st, scratch + v.state, sizeof st, hipMemcpyDeviceToHost, stream);
+  e = hipMemcpyAsync(&st, base + v.state, sizeof st, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(out3, scratch + v.out, sizeof(double) * 3, hipMemcpyDeviceToHost, stream);
+    e = hipMemcpyAsync(out3, base + v.out, sizeof(double) * 3, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "variance result");
   if (st.status != 0) {
