@@ -47,7 +47,10 @@ extern "C" {
 #endif
 
 #define CPD_MAX_MODES 8
-#define CPD_MAX_RANK 64
+#define CPD_MAX_RANK 128             /* up to 64 on every path; 65..128 on the grid path
+                                        (CPD_PATH_AUTO picks it) with the Euclidean or
+                                        uniform sampler; batches, the server and
+                                        cpd_variance take R <= 64 */
 #define CPD_MAX_BATCH 1048576
 #define CPD_MAX_PERSISTENT_BATCH 4096  /* largest B of the one-workgroup step */
 #define CPD_MAX_DIM 4096

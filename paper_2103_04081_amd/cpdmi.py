@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcpdmi.so")
 
 MAX_MODES = 8
-MAX_RANK = 64
+MAX_RANK = 128
 
 CPD_OK, CPD_PENDING = 0, 1
 CPD_E_INVALID, CPD_E_OOM, CPD_E_HIP = -1, -2, -3

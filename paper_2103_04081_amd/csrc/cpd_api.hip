@@ -73,14 +73,24 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
       return CPD_E_INVALID;
     }
   }
-  // the persistent step when it fits (or is asked for), else the grid step
+  // the persistent step when it fits (or is asked for), else the grid step;
+  // ranks beyond 64 run on the grid step only, with the kernels compiled for
+  // kWideRt rank tiles
   const int RT = (p->R + 15) / 16;
-  const LdsPlan lp = lds_plan(p->N, p->dims, p->R, p->B, RT);
-  const bool fits = p->B <= CPD_MAX_PERSISTENT_BATCH && lp.total <= kLdsBudget;
+  const bool wide_rank = RT > kMaxRankTiles;
+  const int GRT = wide_rank ? kWideRt : RT;
+  if (wide_rank && o->sampler == CPD_SAMPLER_LEVERAGE) {
+    *why = "the leverage sampler takes R <= " + std::to_string(16 * kMaxRankTiles);
+    return CPD_E_INVALID;
+  }
+  const LdsPlan lp = lds_plan(p->N, p->dims, p->R, p->B, wide_rank ? kMaxRankTiles : RT);
+  const bool fits =
+      !wide_rank && p->B <= CPD_MAX_PERSISTENT_BATCH && lp.total <= kLdsBudget;
   w->grid = o->path == CPD_PATH_GRID || (o->path == CPD_PATH_AUTO && !fits);
   w->lds = w->grid ? 0 : lp.total;
   if (!w->grid && !fits) {
-    *why = p->B > CPD_MAX_PERSISTENT_BATCH
+    *why = wide_rank ? "the persistent step takes R <= " + std::to_string(16 * kMaxRankTiles)
+           : p->B > CPD_MAX_PERSISTENT_BATCH
                ? "the persistent step takes B <= " + std::to_string(CPD_MAX_PERSISTENT_BATCH)
                : "problem needs " + std::to_string(lp.total) +
                      " bytes of LDS per workgroup (limit 163840): reduce B, R or the mode sizes";
@@ -90,9 +100,9 @@ cpd_status plan_workspace(const cpd_problem* p, const cpd_options* o, WsPlan* w,
   w->gather_lds = w->refresh_lds = 0;
   if (w->grid) {
     int fb = wide_fibres(p->B);
-    while (fb > kFibrePad && gather_plan(p->N, p->dims, RT, fb).total > kLdsBudget) fb -= kFibrePad;
-    w->gather_lds = gather_plan(p->N, p->dims, RT, fb).total;
-    w->refresh_lds = refresh_plan(p->N, p->dims, p->R, RT).total;
+    while (fb > kFibrePad && gather_plan(p->N, p->dims, GRT, fb).total > kLdsBudget) fb -= kFibrePad;
+    w->gather_lds = gather_plan(p->N, p->dims, GRT, fb).total;
+    w->refresh_lds = refresh_plan(p->N, p->dims, p->R, GRT).total;
     if (w->gather_lds > kLdsBudget || w->refresh_lds > kLdsBudget) {
       *why = "the grid step needs " + std::to_string(std::max(w->gather_lds, w->refresh_lds)) +
              " bytes of LDS per block (limit 163840): reduce R or the mode sizes";
@@ -858,11 +868,19 @@ cpd_status cpd_write_state(cpd_handle* h, const void* buf, size_t bytes) {
   return device_status(h);
 }
 
+// The exact variance is evaluated for R <= 64.
+static bool variance_rank_ok(const cpd_handle* h) {
+  if (h->p.R <= 16 * kMaxRankTiles) return true;
+  set_error("the exact variance takes R <= " + std::to_string(16 * kMaxRankTiles));
+  return false;
+}
+
 cpd_status cpd_variance_workspace_size(cpd_handle* h, int32_t n, size_t* bytes) {
   if (!h || !bytes || n < 0 || n >= h->p.N) {
     set_error("bad argument");
     return CPD_E_INVALID;
   }
+  if (!variance_rank_ok(h)) return CPD_E_INVALID;
   *bytes = variance_scratch_bytes(h->desc, n);
   return CPD_OK;
 }
@@ -874,6 +892,7 @@ cpd_status cpd_variance(cpd_handle* h, int32_t n, int32_t sampler, void* ws, siz
     set_error("bad argument");
     return CPD_E_INVALID;
   }
+  if (!variance_rank_ok(h)) return CPD_E_INVALID;
   cpd_status s = set_device(h);
   if (s != CPD_OK) return s;
   s = device_status(h);
@@ -889,6 +908,7 @@ cpd_status cpd_variance_noalloc(cpd_handle* h, int32_t n, int32_t sampler, doubl
     set_error("bad argument");
     return CPD_E_INVALID;
   }
+  if (!variance_rank_ok(h)) return CPD_E_INVALID;
   cpd_status s = set_device(h);
   if (s != CPD_OK) return s;
   s = device_status(h);

@@ -15,6 +15,9 @@ namespace cpdmi {
 
 constexpr int kMaxModes = CPD_MAX_MODES;
 constexpr int kMaxRank = CPD_MAX_RANK;
+constexpr int kMaxRankTiles = 4;        // rank tiles (R <= 64) of the persistent step, batches,
+                                        // the server, leverage scores and the variance
+constexpr int kWideRt = 8;              // the grid step's rank tiles for 4 < ceil(R/16) <= 8
 constexpr int kBlock = 512;             // threads of the persistent step workgroup
 constexpr int kWaves = kBlock / 64;
 constexpr int kFitBlock = 512;

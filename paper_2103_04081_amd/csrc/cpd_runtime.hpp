@@ -24,6 +24,7 @@ hipError_t launch_copy0_from_staged(const void* staged, const ChainDesc& d, hipS
 struct FitPlan {
   int32_t blocks[2];  // light, heavy
   size_t lds[2];      // dynamic LDS of the inner pass per group
+  int32_t passes;     // inner passes over 64 ranks each (2 when some R > 64)
 };
 inline int fit_table_len(int nchains) { return 3 * (nchains + 1); }
 FitPlan plan_fit(const ChainDesc* host_descs, int nchains, int32_t* tables);

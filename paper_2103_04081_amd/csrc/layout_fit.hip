@@ -11,6 +11,8 @@
 // with ||[[A]]||^2 = 1^T (hadamard_k A^(k)T A^(k)) 1 in FP64 and
 // <X, [[A]]> = sum_j sum_i x_j(i) (A^(1)(i,:) . z_j) streamed over copy 0
 // (z_j the KRP row of the fibre's multi-index), FP64 accumulation.
+#include <algorithm>
+
 #include "cpd_runtime.hpp"
 
 namespace cpdmi {
@@ -203,10 +205,13 @@ __device__ __forceinline__ int fit_chain_of(const int32_t* start, int nchains, i
   return lo;
 }
 
+// Inner pass over the ranks [r_off, r_off + 64) (up to four rank tiles);
+// R > 64 takes a second pass (r_off = 64) whose sums are added to the first's.
 template <typename T, bool INNER>
 __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc* __restrict__ descs,
                                                                 const int32_t* __restrict__ start,
-                                                                int nchains, int lds_floats) {
+                                                                int nchains, int lds_floats,
+                                                                int r_off) {
   extern __shared__ __align__(16) float a0t[];
   __shared__ double red[kFitBlock / 64];
   constexpr int E = 16 / (int)sizeof(T);  // elements per 16-byte load
@@ -222,7 +227,8 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
   const int64_t rpb = ((J0 + nb - 1) / nb + 15) / 16 * 16;
   const int64_t r0 = (int64_t)b * rpb;
   const int64_t r1 = r0 + rpb < J0 ? r0 + rpb : J0;
-  const int RT = (R + 15) / 16;
+  if (INNER && r_off >= R) return;  // a second pass only for R > 64
+  const int RT = min(4, (R - r_off + 15) / 16);
   const int P = fit_a0_stride(I0);
   // BF16 storage: the stored values feed v_mfma_f32_16x16x32_bf16 directly,
   // A^(1) = hi + lo as two BF16 terms (16 significant bits; products exact
@@ -240,8 +246,8 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
     for (int e = tid; e < 16 * RT * P; e += kFitBlock) a0t[e] = 0.f;
     __syncthreads();
     for (int e = tid; e < I0 * R; e += kFitBlock) {
-      const int i = e / R, col = e - i * R;
-      a0t[col * P + i] = A0[e];
+      const int i = e / R, col = e - i * R - r_off;
+      if (col >= 0 && col < 16 * RT) a0t[col * P + i] = A0[e];
     }
     __syncthreads();
   }
@@ -249,7 +255,8 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
     for (int e = tid; e < 2 * 16 * RT * P16; e += kFitBlock) a0h[e] = 0;
     __syncthreads();
     for (int e = tid; e < I0 * R; e += kFitBlock) {
-      const int i = e / R, col = e - i * R;
+      const int i = e / R, col = e - i * R - r_off;
+      if (col < 0 || col >= 16 * RT) continue;
       const float v = A0[e];
       const uint16_t h = f32_to_bf16_rne(v);
       a0h[col * P16 + i] = h;
@@ -317,7 +324,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
           if (rt < RT) {
-            const int col = 16 * rt + rq;
+            const int col = 16 * rt + rq;   // relative to r_off
 #pragma unroll
             for (int s4 = 0; s4 < E / 4; ++s4) {
               f4 bv;
@@ -327,7 +334,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                   const int i = ib + 4 * s4 + s;
-                  bv[s] = (i < I0 && col < R) ? A0[(int64_t)i * R + col] : 0.f;
+                  bv[s] = (i < I0 && r_off + col < R) ? A0[(int64_t)i * R + r_off + col] : 0.f;
                 }
               }
 #pragma unroll
@@ -389,7 +396,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
         const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]) + (int64_t)ik * R;
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-          const int col = 16 * rt + rq;
+          const int col = r_off + 16 * rt + rq;
           if (rt < RT) w[rt] *= col < R ? Ak[col] : 0.f;
         }
       }
@@ -404,7 +411,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
         if (i1 < I1) {
 #pragma unroll
           for (int rt = 0; rt < 4; ++rt) {
-            const int col = 16 * rt + rq;
+            const int col = r_off + 16 * rt + rq;
             z[rt] = (rt < RT && col < R) ? A1[(int64_t)i1 * R + col] * w[rt] : 0.f;
           }
         } else {
@@ -420,7 +427,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
             const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]) + (int64_t)ik * R;
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt) {
-              const int col = 16 * rt + rq;
+              const int col = r_off + 16 * rt + rq;
               if (rt < RT) z[rt] *= col < R ? Ak[col] : 0.f;
             }
           }
@@ -439,7 +446,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
   if (tid == 0) {
     double sum = 0.0;
     for (int w = 0; w < kFitBlock / 64; ++w) sum += red[w];
-    dp->parts[b] = sum;
+    dp->parts[b] = r_off ? dp->parts[b] + sum : sum;
   }
 }
 
@@ -450,7 +457,7 @@ template <bool INNER>
 __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __restrict__ descs,
                                                          const int32_t* __restrict__ start) {
   __shared__ double red[16];
-  __shared__ double had[kMaxRank * kMaxRank];
+  __shared__ double had[1024];  // Hadamard products when R^2 < 1024
   __shared__ double slice[1024];
   const ChainDesc* dp = descs + blockIdx.x;
   if (!dp->active || (INNER && dp->state->done)) return;
@@ -472,16 +479,24 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
   // ||[[A]]||^2 = sum_{r,c} prod_k (A^(k)T A^(k))_{rc}.  Factor rows pass
   // through LDS in chunks; thread (pair p, slice sl) sums rows sl, sl +
   // slices, ... of the chunk for its pair in FP64; slices combine in order.
+  // With R^2 >= 1024 pairs every thread owns the pairs tid + 1024 q and
+  // keeps their Hadamard products in registers.
   const int R = dp->R, N = dp->N, R2 = R * R;
   const int slices = R2 >= 1024 ? 1 : 1024 / R2;
   constexpr int kRows = 64;
+  constexpr int kPq = (kMaxRank * kMaxRank + 1023) / 1024;  // pairs per thread
   __shared__ float rows[kRows * kMaxRank];
-  for (int p = tid; p < R2; p += blockDim.x) had[p] = 1.0;
+  double hp[kPq];
+#pragma unroll
+  for (int q = 0; q < kPq; ++q) hp[q] = 1.0;
+  for (int p = tid; p < R2 && slices > 1; p += blockDim.x) had[p] = 1.0;
   for (int k = 0; k < N; ++k) {
     const CPD_GLOBAL float* A = gmem((const float*)dp->A[k]);
     const int Ik = dp->dims[k];
-    double g[4] = {0.0, 0.0, 0.0, 0.0};  // pairs tid, tid + 1024, ... (slices == 1)
-    double gs = 0.0;                     // pair tid % R2, slice tid / R2
+    double g[kPq];  // pairs tid + 1024 q (slices == 1)
+#pragma unroll
+    for (int q = 0; q < kPq; ++q) g[q] = 0.0;
+    double gs = 0.0;  // pair tid % R2, slice tid / R2
     for (int i0 = 0; i0 < Ik; i0 += kRows) {
       const int nr = Ik - i0 < kRows ? Ik - i0 : kRows;
       __syncthreads();
@@ -489,7 +504,7 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
       __syncthreads();
       if (slices == 1) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kPq; ++q) {
           const int p = tid + q * 1024;
           if (p < R2) {
             const int r = p / R, cc = p - r * R;
@@ -507,8 +522,8 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
     __syncthreads();
     if (slices == 1) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (tid + q * 1024 < R2) had[tid + q * 1024] *= g[q];
+      for (int q = 0; q < kPq; ++q)
+        if (tid + q * 1024 < R2) hp[q] *= g[q];
     } else {
       if (tid / R2 < slices) slice[tid] = gs;
       __syncthreads();
@@ -521,7 +536,13 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
     __syncthreads();
   }
   double h = 0.0;
-  for (int p = tid; p < R2; p += blockDim.x) h += had[p];
+  if (slices == 1) {
+#pragma unroll
+    for (int q = 0; q < kPq; ++q)
+      if (tid + q * 1024 < R2) h += hp[q];
+  } else {
+    for (int p = tid; p < R2; p += blockDim.x) h += had[p];
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o);
   if (lane == 0) red[wave] = h;
@@ -545,7 +566,7 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
 constexpr size_t kFitLightLds = 32 * 1024;  // groups the inner pass by staged LDS
 
 FitPlan plan_fit(const ChainDesc* descs, int nchains, int32_t* tables) {
-  FitPlan fp{{0, 0}, {0, 0}};
+  FitPlan fp{{0, 0}, {0, 0}, 1};
   int32_t* all = tables;
   int32_t* grp[2] = {tables + (nchains + 1), tables + 2 * (nchains + 1)};
   int32_t acc = 0, accg[2] = {0, 0};
@@ -559,7 +580,9 @@ FitPlan plan_fit(const ChainDesc* descs, int nchains, int32_t* tables) {
     int64_t nb = (J0 + kFitRowsMin - 1) / kFitRowsMin;
     if (nb < 1) nb = 1;
     if (nb > kFitParts) nb = kFitParts;
-    const size_t rt16 = 16 * (size_t)((d.R + 15) / 16);
+    // one inner pass stages at most 64 rank columns
+    const size_t rt16 = std::min<size_t>(16 * (size_t)((d.R + 15) / 16), 64);
+    if (d.R > 64) fp.passes = 2;
     const size_t need32 = sizeof(float) * rt16 * fit_a0_stride(d.dims[0]);
     const size_t need16 = 2 * sizeof(uint16_t) * rt16 * fit_a0_stride16(d.dims[0]);
     size_t need = (d.dtype == CPD_BF16 && need16 <= kFitLdsMax) ? need16 : need32;
@@ -586,29 +609,32 @@ hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_tables, int nch
   ea = set_lds_limit_once((const void*)fit_partial_kernel<uint16_t, true>, (int)kFitLdsMax,
                           &attr_bf16);
   if (ea != hipSuccess) return ea;
-  for (int g = 0; g < 2; ++g) {
-    if (fp.blocks[g] == 0) continue;
-    const int32_t* tab = d_tables + (g + 1) * (nchains + 1);
-    const dim3 grid((unsigned)fp.blocks[g]);
-    const size_t lds = inner ? fp.lds[g] : 0;
-    const int lds_floats = (int)(lds / sizeof(float));
-    if (dtype == CPD_BF16) {
-      if (inner)
-        hipLaunchKernelGGL((fit_partial_kernel<uint16_t, true>), grid, dim3(kFitBlock), lds, stream,
-                           d_descs, tab, nchains, lds_floats);
-      else
-        hipLaunchKernelGGL((fit_partial_kernel<uint16_t, false>), grid, dim3(kFitBlock), 0, stream,
-                           d_descs, tab, nchains, 0);
-    } else {
-      if (inner)
-        hipLaunchKernelGGL((fit_partial_kernel<float, true>), grid, dim3(kFitBlock), lds, stream,
-                           d_descs, tab, nchains, lds_floats);
-      else
-        hipLaunchKernelGGL((fit_partial_kernel<float, false>), grid, dim3(kFitBlock), 0, stream,
-                           d_descs, tab, nchains, 0);
+  for (int pass = 0; pass < (inner ? fp.passes : 1); ++pass) {
+    const int r_off = 64 * pass;
+    for (int g = 0; g < 2; ++g) {
+      if (fp.blocks[g] == 0) continue;
+      const int32_t* tab = d_tables + (g + 1) * (nchains + 1);
+      const dim3 grid((unsigned)fp.blocks[g]);
+      const size_t lds = inner ? fp.lds[g] : 0;
+      const int lds_floats = (int)(lds / sizeof(float));
+      if (dtype == CPD_BF16) {
+        if (inner)
+          hipLaunchKernelGGL((fit_partial_kernel<uint16_t, true>), grid, dim3(kFitBlock), lds,
+                             stream, d_descs, tab, nchains, lds_floats, r_off);
+        else
+          hipLaunchKernelGGL((fit_partial_kernel<uint16_t, false>), grid, dim3(kFitBlock), 0,
+                             stream, d_descs, tab, nchains, 0, 0);
+      } else {
+        if (inner)
+          hipLaunchKernelGGL((fit_partial_kernel<float, true>), grid, dim3(kFitBlock), lds,
+                             stream, d_descs, tab, nchains, lds_floats, r_off);
+        else
+          hipLaunchKernelGGL((fit_partial_kernel<float, false>), grid, dim3(kFitBlock), 0, stream,
+                             d_descs, tab, nchains, 0, 0);
+      }
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
   }
   if (inner)
     hipLaunchKernelGGL((fit_final_kernel<true>), dim3(nchains), dim3(1024), 0, stream, d_descs,

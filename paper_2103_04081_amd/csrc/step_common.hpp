@@ -57,17 +57,18 @@ __device__ inline int wht_index(int k, int rt, int lane, int RT) {
 }
 
 // ---------------------------------------------------------------------------
-// CDF of mode n from the factor rows in mbuf (row i at mbuf[i * ms]).
+// CDF of mode n from its factor rows in LDS (row i at mb[i * ms]).
 // ---------------------------------------------------------------------------
 template <int RT>
-__device__ __forceinline__ int refresh_cdf(const ChainDesc* dp, const Smem& S, int n) {
+__device__ __forceinline__ int refresh_cdf(const ChainDesc* dp, const Smem& S, int n,
+                                           const float* mb, int ms) {
   const int R = dp->R, In = dp->dims[n];
-  const int ms = S.ms;
-  const float* mb = S.mbuf();
   double* w = S.wts();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int err = 0;
-  if (dp->sampler == CPD_SAMPLER_LEVERAGE) {
+  // leverage scores for R <= 64 (refused beyond; the forward solve keeps a
+  // row in registers)
+  if constexpr (RT <= kMaxRankTiles) if (dp->sampler == CPD_SAMPLER_LEVERAGE) {
     // leverage scores l_i = ||L^{-1} a_i||^2 with L L^T = A^T A (FP64)
     double* G = S.gram();
     const int npairs = R * (R + 1) / 2;
@@ -300,10 +301,17 @@ __device__ __forceinline__ void compute_gs(const Smem& S) {
         g = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[j], b, g, 0, 0, 0);
       }
     }
+    if constexpr (kparts == 1) {
+      // one part per tile: straight to Gs
 #pragma unroll
-    for (int e = 0; e < 4; ++e) gsp[it * 256 + (4 * fl + e) * 16 + cl] = g[e];
+      for (int e = 0; e < 4; ++e) S.gs()[(rt * 16 + 4 * fl + e) * S.rp16 + ct * 16 + cl] = g[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) gsp[it * 256 + (4 * fl + e) * 16 + cl] = g[e];
+    }
   }
   __syncthreads();
+  if constexpr (kparts == 1) return;
   const int rp16 = S.rp16;
   for (int e = threadIdx.x; e < rp16 * rp16; e += NT) {
     const int r = e / rp16, s2 = e - r * rp16;
@@ -357,6 +365,7 @@ __device__ __forceinline__ float update_entry(const UpdateParams& u, float a, fl
   if (u.nonneg) an = fmaxf(an, 0.f);
   return an;
 }
+
 
 // first i in [0, Ik) with C[i] > tg (C ascending, C[Ik-1] > tg)
 __device__ inline int cdf_search(const double* C, int Ik, double tg) {

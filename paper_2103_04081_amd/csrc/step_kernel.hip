@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
         S.mbuf()[i * S.ms + r] = gmem(dp->A[n])[e];
       }
       __syncthreads();
-      err = refresh_cdf<RT>(dp, S, n);
+      err = refresh_cdf<RT>(dp, S, n, S.mbuf(), S.ms);
       __syncthreads();
     }
     if (tid == 0) {
@@ -639,7 +639,7 @@ __global__ void __launch_bounds__(kBlock) chain_kernel(const ChainDesc* __restri
     }
     // ---- 5. distribution of mode n from the new factor -------------------
     if (dp->sampler != CPD_SAMPLER_UNIFORM) {
-      err = refresh_cdf<RT>(dp, S, n);
+      err = refresh_cdf<RT>(dp, S, n, S.mbuf(), S.ms);
       if (err) break;
     }
     __syncthreads();

@@ -298,7 +298,8 @@ __global__ void __launch_bounds__(1024) variance_final_kernel(const ChainDesc* _
                                                               const double* __restrict__ terms,
                                                               double* __restrict__ out) {
   __shared__ double red[16];
-  __shared__ double had[kMaxRank * kMaxRank];
+  constexpr int kVr = 16 * kMaxRankTiles;  // the variance takes R <= 64
+  __shared__ double had[kVr * kVr];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = dp->R, R2 = R * R, In = dp->dims[n];
   double t = 0.0;
@@ -312,8 +313,8 @@ __global__ void __launch_bounds__(1024) variance_final_kernel(const ChainDesc* _
   __syncthreads();
   // H = hadamard_{k != n} A^(k)T A^(k), FP64: every thread takes one (pair,
   // row range) item; the row ranges of a pair are summed in a fixed order
-  // items: npairs * nrg <= max(npairs, blockDim.x) <= kMaxRank (kMaxRank + 1) / 2
-  __shared__ double gpart[kMaxRank * (kMaxRank + 1) / 2];
+  // items: npairs * nrg <= max(npairs, blockDim.x) <= kVr (kVr + 1) / 2
+  __shared__ double gpart[kVr * (kVr + 1) / 2];
   for (int p = tid; p < R2; p += blockDim.x) had[p] = 1.0;
   const int npairs = R * (R + 1) / 2;
   for (int k = 0; k < dp->N; ++k) {
@@ -467,7 +468,7 @@ size_t variance_scratch_bytes(const ChainDesc& hd, int n) {
 // (cpd_variance_noalloc): one array per device, held until the process
 // ends.  Its size covers every problem within the library's limits: the
 // parts of M are capped at kVarPartBudget, M itself takes at most
-// CPD_MAX_DIM * CPD_MAX_RANK doubles, the CDFs CPD_MAX_MODES * CPD_MAX_DIM
+// CPD_MAX_DIM * 64 doubles (the variance takes R <= 64), the CDFs CPD_MAX_MODES * CPD_MAX_DIM
 // doubles, the rest a few KiB.  In host code the array's name is only a
 // host-side stand-in; kernels and copies use the device address returned by
 // hipGetSymbolAddress for the current device.

@@ -88,16 +88,22 @@ __host__ __device__ inline GatherPlan gather_plan(int N, const int32_t* dims, in
   p.rowoff = take(sizeof(uint32_t) * fb);
   p.wht = take(sizeof(float) * (size_t)fb * rp16);
   p.gs = take(sizeof(float) * (size_t)rp16 * rp16);
-  p.gsp = take(sizeof(float) * 256 * (size_t)(t2 > kGatherWaves ? t2 : kGatherWaves));
+  // Gs partials only when fewer tiles than waves split the fibres (with at
+  // least as many tiles as waves every tile is written straight to gs)
+  p.gsp = take(t2 >= kGatherWaves ? 0 : sizeof(float) * 256 * (size_t)kGatherWaves);
   p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
   p.total = off;
   return p;
 }
 
-// LDS map of the refresh kernel (the CDF of one mode at a time).
+// LDS map of the refresh kernel (the CDF of one mode at a time).  The Gram
+// of the leverage scores is planned for R <= 64 (the sampler is refused
+// beyond).  The factor rows are staged in LDS (mbuf) for R <= 64, and
+// beyond when they fit; otherwise (rows_in_lds = 0) the row sums are read
+// straight from global memory.
 struct RefreshPlan {
   size_t cdf, mbuf, gram, part, red, wts, misc, total;
-  int ms, imax;
+  int ms, imax, rows_in_lds;
 };
 
 __host__ __device__ inline RefreshPlan refresh_plan(int N, const int32_t* dims, int R, int RT) {
@@ -105,20 +111,25 @@ __host__ __device__ inline RefreshPlan refresh_plan(int N, const int32_t* dims, 
   p.imax = 0;
   for (int k = 0; k < N; ++k) p.imax = dims[k] > p.imax ? dims[k] : p.imax;
   p.ms = 16 * RT + 1;
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t o = off;
-    off += (size_t)round_up((int64_t)bytes, 16);
-    return o;
-  };
-  p.cdf = take(sizeof(double) * p.imax);
-  p.mbuf = take(sizeof(float) * (size_t)p.imax * p.ms);
-  p.gram = take(sizeof(double) * (size_t)R * R);
-  p.part = take(sizeof(double) * kBlock);
-  p.red = take(sizeof(double) * 2 * kWaves);
-  p.wts = take(sizeof(double) * (size_t)p.imax);
-  p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
-  p.total = off;
+  const bool small_rank = R <= 16 * kMaxRankTiles;
+  for (int pass = 0; pass < 2; ++pass) {
+    p.rows_in_lds = pass == 0;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      size_t o = off;
+      off += (size_t)round_up((int64_t)bytes, 16);
+      return o;
+    };
+    p.cdf = take(sizeof(double) * p.imax);
+    p.mbuf = take(p.rows_in_lds ? sizeof(float) * (size_t)p.imax * p.ms : 0);
+    p.gram = take(small_rank ? sizeof(double) * (size_t)R * R : 0);
+    p.part = take(sizeof(double) * kBlock);
+    p.red = take(sizeof(double) * 2 * kWaves);
+    p.wts = take(sizeof(double) * (size_t)p.imax);
+    p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
+    p.total = off;
+    if (small_rank || off <= kLdsBudget) break;
+  }
   return p;
 }
 

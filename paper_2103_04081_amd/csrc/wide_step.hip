@@ -488,23 +488,23 @@ __global__ void __launch_bounds__(kBlock) wide_refresh_kernel(const ChainDesc* _
   // every mode's CDF goes to the same LDS region (offset 0)
   if (tid < 8 + kMaxModes) S.misc()[tid] = 0;
   float* mbuf = S.mbuf();
-  const int padc = P.ms - R;
-  for (int e = tid; e < P.imax * padc; e += kBlock) {
-    const int i = e / padc;
-    mbuf[i * P.ms + R + (e - i * padc)] = 0.f;
-  }
   // mode -1: one block per mode
   const int nb = mode >= 0 ? mode : (mode == -1 ? (int)blockIdx.x : ninfo);
   const int ne = nb + 1;
   int err = 0;
   for (int n = nb; n < ne && !err; ++n) {
     const CPD_GLOBAL float* An = gmem(dp->A[n]);
-    for (int e = tid; e < dp->dims[n] * R; e += kBlock) {
-      const int i = e / R;
-      mbuf[i * P.ms + (e - i * R)] = An[e];
+    if (P.rows_in_lds) {
+      for (int e = tid; e < dp->dims[n] * R; e += kBlock) {
+        const int i = e / R;
+        mbuf[i * P.ms + (e - i * R)] = An[e];
+      }
+      __syncthreads();
+      err = refresh_cdf<RT>(dp, S, n, S.mbuf(), S.ms);
+    } else {
+      // rows too large for LDS: the squared row norms from global memory
+      err = refresh_cdf<RT>(dp, S, n, dp->A[n], R);
     }
-    __syncthreads();
-    err = refresh_cdf<RT>(dp, S, n);
     __syncthreads();
   }
   if (tid == 0 && err) st->status = err;
@@ -533,7 +533,8 @@ hipError_t prepare_wide_kernels(int rt, int dtype) {
     case 1: return prepare_rt<1>(dtype);
     case 2: return prepare_rt<2>(dtype);
     case 3: return prepare_rt<3>(dtype);
-    default: return prepare_rt<4>(dtype);
+    case 4: return prepare_rt<4>(dtype);
+    default: return prepare_rt<kWideRt>(dtype);
   }
 }
 
@@ -556,8 +557,10 @@ hipError_t launch_wide_gather(const ChainDesc* d_desc, int rt, int dtype, int nb
                       : gather_rt<2, false>(d_desc, nblocks, lds_bytes, a, stream);
     case 3: return bf ? gather_rt<3, true>(d_desc, nblocks, lds_bytes, a, stream)
                       : gather_rt<3, false>(d_desc, nblocks, lds_bytes, a, stream);
-    default: return bf ? gather_rt<4, true>(d_desc, nblocks, lds_bytes, a, stream)
-                       : gather_rt<4, false>(d_desc, nblocks, lds_bytes, a, stream);
+    case 4: return bf ? gather_rt<4, true>(d_desc, nblocks, lds_bytes, a, stream)
+                      : gather_rt<4, false>(d_desc, nblocks, lds_bytes, a, stream);
+    default: return bf ? gather_rt<kWideRt, true>(d_desc, nblocks, lds_bytes, a, stream)
+                       : gather_rt<kWideRt, false>(d_desc, nblocks, lds_bytes, a, stream);
   }
 }
 
@@ -586,7 +589,8 @@ hipError_t launch_wide_refresh(const ChainDesc* d_desc, int rt, size_t lds_bytes
     case 1: return refresh_rt<1>(d_desc, lds_bytes, info, mode, nmodes, stream);
     case 2: return refresh_rt<2>(d_desc, lds_bytes, info, mode, nmodes, stream);
     case 3: return refresh_rt<3>(d_desc, lds_bytes, info, mode, nmodes, stream);
-    default: return refresh_rt<4>(d_desc, lds_bytes, info, mode, nmodes, stream);
+    case 4: return refresh_rt<4>(d_desc, lds_bytes, info, mode, nmodes, stream);
+    default: return refresh_rt<kWideRt>(d_desc, lds_bytes, info, mode, nmodes, stream);
   }
 }
 

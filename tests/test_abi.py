@@ -144,3 +144,25 @@ def test_rescale_option_validation():
     with pytest.raises(P.CpdError) as e:
         P.cpd_batch_workspace_size(ps, [P.make_options(), P.make_options(rescale_every=5)])
     assert "member 1" in str(e.value) and "rescale_every" in str(e.value)
+
+
+def test_wide_rank_planning():
+    """Ranks 65..128 plan the grid step (also at the paper's Pavia shape, whose
+    factor rows exceed LDS); the leverage sampler, the persistent path and
+    ranks beyond 128 are refused."""
+    import paper_2103_04081_amd as P
+    o = P.make_options(sampler="euclidean")
+    n_auto = P.cpd_workspace_size(P.make_problem([610, 340, 103], 100, 20), o)
+    n_grid = P.cpd_workspace_size(P.make_problem([610, 340, 103], 100, 20),
+                                  P.make_options(sampler="euclidean", path="grid"))
+    assert n_auto == n_grid
+    P.cpd_workspace_size(P.make_problem([40, 33, 29], 128, 60), P.make_options(sampler="uniform"))
+    with pytest.raises(P.CpdError) as e:
+        P.cpd_workspace_size(P.make_problem([40, 33, 29], 70, 60), P.make_options(sampler="leverage"))
+    assert "leverage" in str(e.value)
+    with pytest.raises(P.CpdError) as e:
+        P.cpd_workspace_size(P.make_problem([40, 33, 29], 70, 60),
+                             P.make_options(sampler="euclidean", path="persistent"))
+    assert "R <= 64" in str(e.value)
+    with pytest.raises(P.CpdError):
+        P.cpd_workspace_size(P.make_problem([40, 33, 29], 129, 60), o)

@@ -82,10 +82,10 @@ def test_every_batch_member_f32():
 
 
 # Shapes of the paper's hyperspectral scenes (the data themselves are not
-# available): seeded Gaussian stand-ins of the same sizes, B = 20.  The
-# 610 x 340 x 103 scene is decomposed at R = 100 in the paper; the step kernel
-# holds a factor's rows in LDS and supports R <= 64 (R = 32 at this size), so
-# the largest rank that fits is run instead.
+# available): seeded Gaussian stand-ins of the same sizes, B = 20, on the
+# persistent step (R = 32 on the 610 x 340 x 103 shape covers its path
+# without resident factors; the paper's R = 100 runs on the grid step,
+# tests/test_gpu_wide_rank.py).
 @pytest.mark.parametrize("dims,R,sampler", [((83, 86, 224), 10, "euclidean"),
                                             ((145, 145, 220), 10, "leverage"),
                                             ((610, 340, 103), 32, "euclidean")])
