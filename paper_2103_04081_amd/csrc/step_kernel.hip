@@ -295,14 +295,22 @@ __device__ __forceinline__ bool contract_update(const ChainDesc* dp, const Smem&
 #pragma unroll
     for (int j = 0; j < kFibreBufs - 1; ++j)
       if (j < total) load(xbuf[j], j);
-    for (int c = 0; c < total; c += kFibreBufs) {
+    // The loads are issued unconditionally (past the end they repeat the
+    // last chunk and are never used), so the loop body is straight-line and
+    // the compiler's waits on the load counter stay one chunk behind
+    // (measured: 0.6 us of 19 per step at 300^3).
+    int c = 0;
+    for (; c + kFibreBufs - 1 < total; c += kFibreBufs) {
 #pragma unroll
       for (int j = 0; j < kFibreBufs; ++j) {
-        if (c + j + kFibreBufs - 1 < total)
-          load(xbuf[(j + kFibreBufs - 1) % kFibreBufs], c + j + kFibreBufs - 1);
-        if (c + j < total) compute(xbuf[j], c + j);
+        const int nx = c + j + kFibreBufs - 1;
+        load(xbuf[(j + kFibreBufs - 1) % kFibreBufs], nx < total ? nx : total - 1);
+        compute(xbuf[j], c + j);
       }
     }
+#pragma unroll
+    for (int j = 0; j < kFibreBufs - 1; ++j)
+      if (c + j < total) compute(xbuf[j], c + j);
   }
   if (ks > 1) {
     // K-split: the first part adds -Gs^T A^T, the partial tiles are summed
