@@ -18,6 +18,7 @@ constexpr int kMaxRank = CPD_MAX_RANK;
 constexpr int kMaxRankTiles = 4;        // rank tiles (R <= 64) of the persistent step, batches,
                                         // the server, leverage scores and the variance
 constexpr int kWideRt = 8;              // the grid step's rank tiles for 4 < ceil(R/16) <= 8
+constexpr int kGramParts = 4;           // K-parts of the one-tile leverage Gram (256 doubles each)
 constexpr int kBlock = 512;             // threads of the persistent step workgroup
 constexpr int kWaves = kBlock / 64;
 constexpr int kFitBlock = 512;
@@ -153,6 +154,13 @@ template <typename T>
 __device__ __forceinline__ CPD_GLOBAL T* gmem(T* p) {
   return (CPD_GLOBAL T*)(p);
 }
+// The same for LDS pointers handed to a function that is not inlined (whose
+// generic pointer parameters would otherwise become FLAT accesses).
+#define CPD_LDS __attribute__((address_space(3)))
+template <typename T>
+__device__ __forceinline__ CPD_LDS T* lmem(T* p) {
+  return (CPD_LDS T*)(p);
+}
 
 // Raises a kernel's dynamic-LDS limit once per device (bit d of *done set
 // for device d; concurrent first calls may both set it, which is harmless).
@@ -231,6 +239,21 @@ inline int host_ksplit(int In, int dtype, int B, int R) {
   return ks < 1 ? 1 : ks;
 }
 
+// The Gram region of the leverage refresh: G (16 x 16), a pivot column and
+// the pivots' reciprocals for one rank tile; R x R beyond.
+__host__ __device__ constexpr int gram_doubles(int R, int RT) { return RT == 1 ? 288 : R * R; }
+
+// The partials region of the persistent step: the Gs partials (256 floats
+// per tile or wave) and the leverage refresh's Gram partials (doubles: one
+// per thread, or kGramParts x 256 for one rank tile) share it.
+__host__ __device__ constexpr size_t gram_part_bytes() {
+  return sizeof(double) * (kBlock > 256 * kGramParts ? kBlock : 256 * kGramParts);
+}
+__host__ __device__ constexpr size_t chain_part_bytes(int RT) {
+  const size_t gsp = sizeof(float) * 256 * (size_t)(RT * RT > kWaves ? RT * RT : kWaves);
+  return gsp > gram_part_bytes() ? gsp : gram_part_bytes();
+}
+
 // LDS layout of the persistent step kernel for one descriptor, compiled for
 // RT 16-row rank tiles (RT >= ceil(R / 16)).
 struct LdsPlan {
@@ -271,11 +294,9 @@ __host__ __device__ inline LdsPlan lds_plan(int N, const int32_t* dims, int R, i
   p.wht = take(sizeof(float) * (size_t)p.bpad * p.rp16);
   p.gs = take(sizeof(float) * (size_t)p.rp16 * p.rp16);
   p.mbuf = take(sizeof(float) * (size_t)p.imax * p.ms);
-  p.gram = take(sizeof(double) * (size_t)R * R);
+  p.gram = take(sizeof(double) * (size_t)gram_doubles(R, RT));
   // Gs partials (Gs phase) and the Gram partials (leverage refresh) share
-  const size_t gsp_bytes = sizeof(float) * 256 * (size_t)(t2 > kWaves ? t2 : kWaves);
-  const size_t part_bytes = sizeof(double) * kBlock;
-  p.part = take(gsp_bytes > part_bytes ? gsp_bytes : part_bytes);
+  p.part = take(chain_part_bytes(RT));
   p.gsp = p.part;
   p.red = take(sizeof(double) * 2 * kWaves);
   p.wts = take(sizeof(double) * (size_t)p.imax);

@@ -9,6 +9,7 @@
 namespace cpdmi {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 extern __shared__ __align__(16) unsigned char cpd_smem[];
 
@@ -56,6 +57,145 @@ __device__ inline int wht_index(int k, int rt, int lane, int RT) {
   return ((k >> 2) * RT + rt) * 256 + lane * 4 + (k & 3);
 }
 
+// 1 / d in FP64 from the hardware reciprocal and two Newton steps
+// (r <- r + r (1 - d r)), each one doubling the correct bits.
+__device__ inline double rcp_f64(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// L D L^T = G (L unit lower triangular) of the padded Gram G (16 x 16 in
+// LDS, rows and columns past R zero, padded pivots one) by one wave,
+// right-looking, lane r holding row r (its first NR entries): at pivot j the
+// rows store their column-j entries, every lane reads the column back, and
+// row r subtracts M_rj (M_cj / d_j) from its entries c in (j, NR).  Entries
+// above the diagonal are updated too (never read: the stores and the
+// write-back take c <= r), so the updates need no lane masks; no square
+// roots, one reciprocal per pivot.  Writes L into G's lower triangle, 1 / d_j
+// into dinv (one past R), and 1 into *flag if a pivot d_j falls below
+// kRankTol of its diagonal.  A call of its own: inlined, its 64 registers of
+// rows and column push the step kernel's other values into scratch.
+template <int NR>
+__device__ __noinline__ void ldl_wave(CPD_LDS double* G, CPD_LDS double* col, CPD_LDS double* dinv,
+                                      int R, CPD_LDS int32_t* flag) {
+  const int lane = threadIdx.x & 63;
+  const int row = lane < NR ? lane : NR - 1;  // lanes past NR mirror the last row
+  double g[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) g[k] = G[row * 16 + k];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    if (j < R) {
+      if (lane < NR) col[lane] = g[j];
+      wave_lds_sync();
+      double cv[NR];
+#pragma unroll
+      for (int c = j; c < NR; ++c) cv[c] = col[c];
+      const double d = cv[j];
+      const double diag = G[j * 16 + j];
+      const bool okj = d > kRankTol * diag && isfinite(d);
+      ok = ok && okj;
+      const double inv = rcp_f64(okj ? d : 1.0);
+      const double mrj = g[j];
+#pragma unroll
+      for (int c = j + 1; c < NR; ++c) g[c] -= mrj * (cv[c] * inv);
+      g[j] = lane == j ? 1.0 : mrj * inv;
+      if (lane == 0) dinv[j] = inv;
+      wave_lds_sync();  // the column is read before the next pivot's stores
+    } else if (lane == 0) {
+      dinv[j] = 1.0;
+    }
+  }
+  if (lane < NR) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (k <= lane) G[lane * 16 + k] = g[k];
+  }
+  if (lane == 0 && !ok) *flag = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Leverage scores l_i = a_i^T (A^T A)^{-1} a_i = sum_j y_j^2 / d_j with
+// L D L^T = A^T A (FP64) and L y = a_i, of a mode with R <= 16, into wts();
+// everything padded to 16 ranks: the Gram's rows and columns past R are zero
+// and its padded pivots one, so L and D are the identity there.  LDS:
+// gram() holds G (16 x 16, then L in its lower triangle), gram() + 256 the
+// pivot column, gram() + 272 the 1 / d_j; part() the Gram partials
+// (kGramParts x 256).  Returns CPD_E_RANK_DEFICIENT when a pivot falls below
+// kRankTol of its diagonal.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int leverage_one_tile(const ChainDesc* dp, const Smem& S, int n,
+                                                 const float* mb, int ms) {
+  const int R = dp->R, In = dp->dims[n];
+  const int lane = threadIdx.x & 63, wave = uniform_int(threadIdx.x >> 6);
+  double* G = S.gram();
+  double* col = G + 256;
+  double* rinv = G + 272;
+  double* part = S.part();
+  double* w = S.wts();
+  // G = A^T A on the FP64 matrix cores (v_mfma_f64_16x16x4f64): the A and B
+  // operands are the same value, lane l holding a_{4s + l/16}(l % 16) for
+  // K-step s; element q of lane l's result is G(4q + l/16, l % 16).  Wave
+  // p < kGramParts sums the K-steps p, p + kGramParts, ...; the partials are
+  // added in order (every kernel that refreshes a leverage CDF sums in this
+  // order, so they all give the same bits).
+  constexpr int kp = kGramParts;
+  if (wave < kp) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int nks = (In + 3) >> 2;
+    const int r = lane & 15;
+    const int rc = r < R ? r : R - 1;  // loads stay in the rows; zeros are selected
+#pragma unroll 4
+    for (int s = wave; s < nks; s += kp) {
+      const int i = 4 * s + (lane >> 4);
+      const float v = mb[(i < In ? i : In - 1) * ms + rc];
+      const double x = (i < In && r < R) ? (double)v : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[wave * 256 + (4 * q + (lane >> 4)) * 16 + r] = acc[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    double g = 0.0;
+    for (int p = 0; p < kp; ++p) g += part[p * 256 + threadIdx.x];
+    const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
+    if (rr == cc && rr >= R) g = 1.0;
+    G[threadIdx.x] = g;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    ldl_wave<16>(lmem(G), lmem(col), lmem(rinv), R, lmem(S.misc() + 2));
+  }
+  __syncthreads();
+  const int err = S.misc()[2] ? CPD_E_RANK_DEFICIENT : 0;
+  // l_i = sum_j y_j^2 / d_j with L y = a_i (forward substitution, one row
+  // per thread, y in registers)
+  for (int i = threadIdx.x; i < In; i += kBlock) {
+    double y[16];
+    double l = 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j < R) {
+        double v = (double)mb[i * ms + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v -= G[j * 16 + k] * y[k];
+        y[j] = v;
+        l += (v * v) * rinv[j];
+      } else {
+        y[j] = 0.0;
+      }
+    }
+    w[i] = l;
+  }
+  __syncthreads();
+  return err;
+}
+
 // ---------------------------------------------------------------------------
 // CDF of mode n from its factor rows in LDS (row i at mb[i * ms]).
 // ---------------------------------------------------------------------------
@@ -66,9 +206,12 @@ __device__ __forceinline__ int refresh_cdf(const ChainDesc* dp, const Smem& S, i
   double* w = S.wts();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int err = 0;
-  // leverage scores for R <= 64 (refused beyond; the forward solve keeps a
-  // row in registers)
-  if constexpr (RT <= kMaxRankTiles) if (dp->sampler == CPD_SAMPLER_LEVERAGE) {
+  if constexpr (RT == 1) {
+    if (dp->sampler == CPD_SAMPLER_LEVERAGE) err = leverage_one_tile(dp, S, n, mb, ms);
+  }
+  // leverage scores for 16 < R <= 64 (refused beyond; the forward solve keeps
+  // a row in registers)
+  if constexpr (RT > 1 && RT <= kMaxRankTiles) if (dp->sampler == CPD_SAMPLER_LEVERAGE) {
     // leverage scores l_i = ||L^{-1} a_i||^2 with L L^T = A^T A (FP64)
     double* G = S.gram();
     const int npairs = R * (R + 1) / 2;

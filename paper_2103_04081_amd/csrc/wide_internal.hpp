@@ -122,8 +122,8 @@ __host__ __device__ inline RefreshPlan refresh_plan(int N, const int32_t* dims, 
     };
     p.cdf = take(sizeof(double) * p.imax);
     p.mbuf = take(p.rows_in_lds ? sizeof(float) * (size_t)p.imax * p.ms : 0);
-    p.gram = take(small_rank ? sizeof(double) * (size_t)R * R : 0);
-    p.part = take(sizeof(double) * kBlock);
+    p.gram = take(small_rank ? sizeof(double) * (size_t)gram_doubles(R, RT) : 0);
+    p.part = take(gram_part_bytes());
     p.red = take(sizeof(double) * 2 * kWaves);
     p.wts = take(sizeof(double) * (size_t)p.imax);
     p.misc = take(sizeof(int32_t) * (8 + kMaxModes));
