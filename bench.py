@@ -29,16 +29,16 @@ ETA = 5.0
 
 # HBM traffic of the step kernel on this workload, from FETCH_SIZE and WRITE_SIZE counter runs
 # scaled by a 256 MiB device copy (FETCH x2.000, WRITE x1.000), 5000-step dispatch.  Valid only
-# for the kernel sources it was taken on: reported as null once either hash differs.
+# for the kernel sources it was taken on: reported as null once any hash differs.
 MEASURED_TRAFFIC = {
-    "bytes_per_step": 127947.6 * 1024 / 5000,
+    "bytes_per_step": (2.0 * 63625.375 + 1574.78125) * 1024 / 5000,
     "sources": {
         "paper_2103_04081_amd/csrc/step_kernel.hip":
-            "ca412cf9d60a8264259e2535acdd5accf48ca662304a2ae46313ce6141563fb2",
+            "836006f5c15d226f994dc6eda5e19166cd9b8ba157fb0c3f7073b661f344820b",
         "paper_2103_04081_amd/csrc/step_common.hpp":
-            "05b06dd9a2723fcf15382e99bb4dd57f297bff4137f06dc960ba474ef44c9787",
+            "76aa2143d8b948f8b1dd56199d62bbce7d11d82870f233957898644ee0276b2d",
         "paper_2103_04081_amd/csrc/cpd_internal.hpp":
-            "abd905e85ca86c7b3206ed80f57f48e63c56e236025950efd944a40f2ff6b8ee",
+            "fced12af7d94d43adc3d803933a7cff94dfaae77ff8a20b7ea606b748e0303b3",
     },
     "profile": "profiles/chain_kernel_300cube_R10_B256_f32.md",
 }
@@ -93,6 +93,11 @@ def parse():
     ap.add_argument("--no-rescale", action="store_true", help="skip the rescaling-cost section")
     ap.add_argument("--rescale-only", action="store_true",
                     help="run only the rescaling-cost section (profiling)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed steps of the main workload (and the CPU baseline unless "
+                         "--no-cpu-baseline): the form the profiles are taken on")
+    ap.add_argument("--fit-only", action="store_true",
+                    help="only time the fit check (300^3 FP32 and 120^4 BF16, 40 fits each)")
     ap.add_argument("--grid-only", action="store_true",
                     help="run only the large-batch grid sweep (profiling)")
     ap.add_argument("--grid-b", default="4096,16384,65536,131072,262144",
@@ -223,6 +228,9 @@ def cpu_baseline(w, seconds):
 
 def main():
     args = parse()
+    if args.headline_only:
+        args.no_fit = args.no_batch = args.no_rescale = args.no_grid = True
+        args.no_variance = args.no_serve = args.no_oracle_extra = True
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
@@ -247,6 +255,9 @@ def main():
     X32 = np.asfortranarray(w["X"].astype(np.float32))
     if args.rescale_only:
         print(json.dumps({"rescale": rescale_cost(w, X32)}), flush=True)
+        return
+    if args.fit_only:
+        print(json.dumps({"fit_cost": fit_cost(w, X32)}), flush=True)
         return
     if args.grid_only:
         out = {"grid_sweep": grid_sweep(w, X32, args)}
@@ -289,12 +300,13 @@ def main():
     if not args.no_batch:
         extra["batch"] = batch_bench(args.batch_count, seq=not args.no_seq)
         progress("batch")
-    extra["small_workload"] = small_workload()
-    progress("small_workload")
-    extra["four_way"] = four_way()
-    progress("four_way")
-    extra["scenes"] = scenes()
-    progress("scenes")
+    if not args.headline_only:
+        extra["small_workload"] = small_workload()
+        progress("small_workload")
+        extra["four_way"] = four_way()
+        progress("four_way")
+        extra["scenes"] = scenes()
+        progress("scenes")
     if not args.no_rescale:
         extra["rescale"] = rescale_cost(w, X32)
         progress("rescale")
@@ -688,6 +700,43 @@ def small_workload(steps=2000):
         ms = ev0.elapsed_time(ev1)
         out[sampler] = {"steps_per_s": steps / (ms / 1e3), "us_per_step": ms * 1e3 / steps,
                         "fit_after": dec.fit(), "t": dec.t - t0}
+        dec.close()
+    return out
+
+
+def fit_cost(w, X32, reps=40):
+    """The explicit fit check (a8) on the main workload (300^3 FP32) and on
+    the 120^4 BF16 tensor: host wall time per fit (launches of the partial
+    and final kernels plus the state read-back), and the algorithmic bytes
+    of its stream (one copy of the tensor)."""
+    import numpy as np
+
+    import cpd_inputs as ci
+    import paper_2103_04081_amd as P
+
+    out = {}
+    cases = [("300^3 FP32, R=10", lambda: P.Decomposition(X32, w["A0"], B=w["B"], eta=ETA,
+                                                           storage="f32", seed=w["seed"]),
+              w["dims"], 4)]
+    spec = {"dims": (120, 120, 120, 120), "R": 20, "data_seed": 1003, "init_seed": 2003,
+            "snr_db": 30.0}
+    X4, A04 = ci.device_problem(spec, "cuda")
+    cases.append(("120^4 BF16, R=20", lambda: P.Decomposition(X4, A04, B=512, eta=1.5,
+                                                              storage="bf16", seed=3003),
+                  spec["dims"], 2))
+    for name, make, dims, s in cases:
+        dec = make()
+        dec.step(10)
+        dec.sync()
+        for _ in range(5):
+            dec.fit()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f = dec.fit()
+        dt = (time.perf_counter() - t0) / reps
+        ld0 = (dims[0] + 63) // 64 * 64
+        nbytes = int(np.prod(dims[1:])) * ld0 * s
+        out[name] = {"host_us_per_fit": dt * 1e6, "stream_bytes": nbytes, "fit": f}
         dec.close()
     return out
 

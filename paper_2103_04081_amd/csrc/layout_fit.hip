@@ -450,6 +450,23 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
   }
 }
 
+// The fit from <X, [[A]]> (total) and the 16 wave sums of ||[[A]]||^2 in
+// red (thread 0 of the final kernel), and the automatic stop.
+__device__ inline void finish_fit(const ChainDesc* dp, double total, const double* red) {
+  double xh = 0.0;
+  for (int w = 0; w < 16; ++w) xh += red[w];
+  ChainState* st = dp->state;
+  st->inner = total;
+  st->xhat2 = xh;
+  st->fit = 1.0 - (st->x2 - 2.0 * total + xh) / st->x2;
+  if (dp->autostop && ((dp->fit_target > 0.0 && st->fit >= dp->fit_target) ||
+                       (dp->step_limit > 0 && st->t >= dp->step_limit) || st->status != 0)) {
+    st->done = 1;
+    st->t_done = st->t;
+    st->clock_done = (int64_t)wall_clock64();
+  }
+}
+
 // Final reduction, one block per decomposition.  Norm pass: state->x2.
 // Inner pass: <X, [[A]]>, ||[[A]]||^2 from the Gram matrices (FP64, rows
 // split over threads, combined in a fixed order) and the fit.
@@ -457,84 +474,229 @@ template <bool INNER>
 __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __restrict__ descs,
                                                          const int32_t* __restrict__ start) {
   __shared__ double red[16];
-  __shared__ double had[1024];  // Hadamard products when R^2 < 1024
+  __shared__ double had[4096];  // Hadamard products (R <= 64)
   __shared__ double slice[1024];
   const ChainDesc* dp = descs + blockIdx.x;
   if (!dp->active || (INNER && dp->state->done)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = start[blockIdx.x + 1] - start[blockIdx.x];
-  double s = 0.0;
-  for (int p = tid; p < nb; p += blockDim.x) s += dp->parts[p];
+  // the partial sums p = tid, tid + 1024, ... (loaded now, summed when
+  // needed: the small-R inner pass forms the Grams meanwhile)
+  static_assert(kFitParts <= 4 * 1024, "four partials per thread");
+  double pv[4];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) red[wave] = s;
-  __syncthreads();
-  double total = 0.0;
-  for (int w = 0; w < (int)(blockDim.x / 64); ++w) total += red[w];
-  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    const int p = tid + 1024 * q;
+    const double v = dp->parts[p < nb ? p : 0];
+    pv[q] = p < nb ? v : 0.0;
+  }
+  auto sum_parts = [&]() {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s += pv[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) t += red[w];
+    __syncthreads();
+    return t;
+  };
   if (!INNER) {
+    const double total = sum_parts();
     if (tid == 0) dp->state->x2 = total;
     return;
   }
-  // ||[[A]]||^2 = sum_{r,c} prod_k (A^(k)T A^(k))_{rc}.  Factor rows pass
-  // through LDS in chunks; thread (pair p, slice sl) sums rows sl, sl +
-  // slices, ... of the chunk for its pair in FP64; slices combine in order.
-  // With R^2 >= 1024 pairs every thread owns the pairs tid + 1024 q and
-  // keeps their Hadamard products in registers.
   const int R = dp->R, N = dp->N, R2 = R * R;
+  __shared__ float rows[64 * kMaxRank];
+  if (R <= 64) {
+    // Up to four rank tiles: the modes' Grams on the FP64 matrix cores
+    // (v_mfma_f64_16x16x4f64), tile (rt, ct) of G_k = A^(k)T A^(k) with lane
+    // l holding A^(k)(4s + l/16, 16 rt + l % 16) as the A operand and
+    // A^(k)(4s + l/16, 16 ct + l % 16) as the B operand for K-step s; element
+    // q of lane l's result is G_k(16 rt + 4q + l/16, 16 ct + l % 16).  The
+    // items (mode k, tile t, K-part p), p fastest, kp a power of two with
+    // N T kp <= 16 where it can be, go to the 16 waves in rounds of 16 (one
+    // round for small R: every mode's loads in flight together, straight
+    // from global memory).  Per round the items' tiles go to LDS and each
+    // element of had (the Hadamard product over the modes) is multiplied by
+    // its (k, t) groups' part sums, in item order.  Ranks past R load zeros,
+    // so their Gram entries and products are zero.
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    double* part = (double*)rows;  // 16 x 256 doubles
+    const int RT = (R + 15) / 16, T = RT * RT;
+    int kp = 1;
+    while (2 * kp * N * T <= 16) kp *= 2;
+    const int nitems = N * T * kp;
+    const int rq = lane & 15, kq = lane >> 4;
+    for (int e = tid; e < T * 256; e += blockDim.x) had[e] = 1.0;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);  // uniform: the items' loops are scalar
+    for (int r0 = 0; r0 < nitems; r0 += 16) {
+      const int item = r0 + wv;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      if (item < nitems) {
+        const int kpart = item % kp, kt = item / kp;
+        const int k = kt / T, tile = kt - k * T;
+        const int rt = tile / RT, ct = tile - rt * RT;
+        const int ra = 16 * rt + rq, rb = 16 * ct + rq;
+        // loads clamped into the factor and issued unconditionally (several
+        // in flight); out-of-range entries are replaced by zeros after
+        const int rac = ra < R ? ra : R - 1, rbc = rb < R ? rb : R - 1;
+        const CPD_GLOBAL float* A = gmem((const float*)dp->A[k]);
+        const int Ik = dp->dims[k], nks = (Ik + 3) >> 2;
+        auto kstep = [&](int st, float& va, float& vb) {
+          const int i = 4 * st + kq;
+          const int64_t row = (int64_t)(i < Ik ? i : Ik - 1) * R;
+          va = A[row + rac];
+          vb = A[row + rbc];
+        };
+        auto mac = [&](int st, float va, float vb) {
+          const int i = 4 * st + kq;
+          const double xa = (i < Ik && ra < R) ? (double)va : 0.0;
+          const double xb = (i < Ik && rb < R) ? (double)vb : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, xb, acc, 0, 0, 0);
+        };
+        // eight K-steps' loads in flight before their products
+        int st = kpart;
+        for (; st + 7 * kp < nks; st += 8 * kp) {
+          float va[8], vb[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) kstep(st + u * kp, va[u], vb[u]);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) mac(st + u * kp, va[u], vb[u]);
+        }
+        for (; st < nks; st += kp) {
+          float va, vb;
+          kstep(st, va, vb);
+          mac(st, va, vb);
+        }
+      }
+      __syncthreads();  // the previous round's tiles are consumed
+      if (item < nitems) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) part[wv * 256 + (4 * q + kq) * 16 + rq] = acc[q];
+      }
+      __syncthreads();
+      for (int e = tid; e < T * 256; e += blockDim.x) {
+        const int te = e >> 8, o = e & 255;
+        for (int g0 = r0; g0 < r0 + 16 && g0 < nitems; g0 += kp) {
+          if ((g0 / kp) % T != te) continue;
+          double gk = 0.0;
+          for (int p2 = 0; p2 < kp; ++p2) gk += part[(g0 - r0 + p2) * 256 + o];
+          had[e] *= gk;
+        }
+      }
+    }
+    __syncthreads();
+    const double total = sum_parts();
+    double h = 0.0;
+    for (int e = tid; e < T * 256; e += blockDim.x) h += had[e];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o);
+    if (lane == 0) red[wave] = h;
+    __syncthreads();
+    if (tid == 0) finish_fit(dp, total, red);
+    return;
+  }
+  const double total = sum_parts();
+  // ||[[A]]||^2 = sum_{r,c} prod_k (A^(k)T A^(k))_{rc}.  The factors pass
+  // through LDS in chunks of as many rows as the buffer holds (a whole
+  // factor at small R), mode after mode; the next chunk is loaded into
+  // registers while the current one is summed, so the chunks' round trips
+  // to memory overlap the sums.  Thread (pair p, slice sl) sums rows sl,
+  // sl + slices, ... of the chunk for its pair in FP64 (two accumulators,
+  // even and odd steps); slices combine in order.  With R^2 >= 1024 pairs
+  // every thread owns the pairs tid + 1024 q (one accumulator each) and
+  // keeps their Hadamard products in registers.
   const int slices = R2 >= 1024 ? 1 : 1024 / R2;
-  constexpr int kRows = 64;
+  constexpr int kRowBuf = 64 * kMaxRank;  // floats
+  constexpr int kPer = kRowBuf / 1024;    // floats of the next chunk per thread
   constexpr int kPq = (kMaxRank * kMaxRank + 1023) / 1024;  // pairs per thread
-  __shared__ float rows[kRows * kMaxRank];
+  const int chunk = kRowBuf / R;  // rows per chunk
   double hp[kPq];
 #pragma unroll
   for (int q = 0; q < kPq; ++q) hp[q] = 1.0;
   for (int p = tid; p < R2 && slices > 1; p += blockDim.x) had[p] = 1.0;
-  for (int k = 0; k < N; ++k) {
-    const CPD_GLOBAL float* A = gmem((const float*)dp->A[k]);
-    const int Ik = dp->dims[k];
-    double g[kPq];  // pairs tid + 1024 q (slices == 1)
+  float nx[kPer];
+  auto fetch = [&](int k, int i0) {
+    const CPD_GLOBAL float* A = gmem((const float*)dp->A[k]) + (int64_t)i0 * R;
+    const int n = (dp->dims[k] - i0 < chunk ? dp->dims[k] - i0 : chunk) * R;
 #pragma unroll
-    for (int q = 0; q < kPq; ++q) g[q] = 0.0;
-    double gs = 0.0;  // pair tid % R2, slice tid / R2
-    for (int i0 = 0; i0 < Ik; i0 += kRows) {
-      const int nr = Ik - i0 < kRows ? Ik - i0 : kRows;
-      __syncthreads();
-      for (int e = tid; e < nr * R; e += blockDim.x) rows[e] = A[(int64_t)i0 * R + e];
-      __syncthreads();
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + 1024 * q;
+      nx[q] = e < n ? A[e] : 0.f;
+    }
+  };
+  double g[kPq];  // pairs tid + 1024 q (slices == 1)
+#pragma unroll
+  for (int q = 0; q < kPq; ++q) g[q] = 0.0;
+  double gs = 0.0;  // pair tid % R2, slice tid / R2
+  fetch(0, 0);
+  for (int k = 0, i0 = 0; k < N;) {
+    const int Ik = dp->dims[k];
+    const int nr = Ik - i0 < chunk ? Ik - i0 : chunk;
+    __syncthreads();  // the previous chunk is summed
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + 1024 * q;
+      if (e < nr * R) rows[e] = nx[q];
+    }
+    __syncthreads();
+    int kn = k, in = i0 + chunk;
+    if (in >= Ik) {
+      kn = k + 1;
+      in = 0;
+    }
+    if (kn < N) fetch(kn, in);
+    if (slices == 1) {
+#pragma unroll
+      for (int q = 0; q < kPq; ++q) {
+        const int p = tid + q * 1024;
+        if (p < R2) {
+          // up to 16 pairs per thread: independent sums enough
+          const int r = p / R, cc = p - r * R;
+#pragma unroll 1
+          for (int i = 0; i < nr; ++i) g[q] += (double)rows[i * R + r] * (double)rows[i * R + cc];
+        }
+      }
+    } else {
+      const int p = tid % R2, sl = tid / R2;
+      if (sl < slices) {
+        const int r = p / R, cc = p - r * R;
+        double a0 = 0.0, a1 = 0.0;
+        int i = sl;
+        for (; i + slices < nr; i += 2 * slices) {
+          a0 += (double)rows[i * R + r] * (double)rows[i * R + cc];
+          a1 += (double)rows[(i + slices) * R + r] * (double)rows[(i + slices) * R + cc];
+        }
+        if (i < nr) a0 += (double)rows[i * R + r] * (double)rows[i * R + cc];
+        gs += a0 + a1;
+      }
+    }
+    if (kn != k) {
+      // mode k complete: its Gram into the Hadamard products
       if (slices == 1) {
 #pragma unroll
         for (int q = 0; q < kPq; ++q) {
-          const int p = tid + q * 1024;
-          if (p < R2) {
-            const int r = p / R, cc = p - r * R;
-            for (int i = 0; i < nr; ++i) g[q] += (double)rows[i * R + r] * (double)rows[i * R + cc];
-          }
+          if (tid + q * 1024 < R2) hp[q] *= g[q];
+          g[q] = 0.0;
         }
       } else {
-        const int p = tid % R2, sl = tid / R2;
-        if (sl < slices) {
-          const int r = p / R, cc = p - r * R;
-          for (int i = sl; i < nr; i += slices) gs += (double)rows[i * R + r] * (double)rows[i * R + cc];
+        if (tid / R2 < slices) slice[tid] = gs;
+        gs = 0.0;
+        __syncthreads();
+        if (tid < R2) {
+          double t = 0.0;
+          for (int q = 0; q < slices; ++q) t += slice[q * R2 + tid];
+          had[tid] *= t;
         }
       }
     }
-    __syncthreads();
-    if (slices == 1) {
-#pragma unroll
-      for (int q = 0; q < kPq; ++q)
-        if (tid + q * 1024 < R2) hp[q] *= g[q];
-    } else {
-      if (tid / R2 < slices) slice[tid] = gs;
-      __syncthreads();
-      if (tid < R2) {
-        double t = 0.0;
-        for (int q = 0; q < slices; ++q) t += slice[q * R2 + tid];
-        had[tid] *= t;
-      }
-    }
-    __syncthreads();
+    k = kn;
+    i0 = in;
   }
+  __syncthreads();
   double h = 0.0;
   if (slices == 1) {
 #pragma unroll
@@ -547,20 +709,7 @@ __global__ void __launch_bounds__(1024) fit_final_kernel(const ChainDesc* __rest
   for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o);
   if (lane == 0) red[wave] = h;
   __syncthreads();
-  if (tid == 0) {
-    double xh = 0.0;
-    for (int w = 0; w < (int)(blockDim.x / 64); ++w) xh += red[w];
-    ChainState* st = dp->state;
-    st->inner = total;
-    st->xhat2 = xh;
-    st->fit = 1.0 - (st->x2 - 2.0 * total + xh) / st->x2;
-    if (dp->autostop && ((dp->fit_target > 0.0 && st->fit >= dp->fit_target) ||
-                         (dp->step_limit > 0 && st->t >= dp->step_limit) || st->status != 0)) {
-      st->done = 1;
-      st->t_done = st->t;
-      st->clock_done = (int64_t)wall_clock64();
-    }
-  }
+  if (tid == 0) finish_fit(dp, total, red);
 }
 
 constexpr size_t kFitLightLds = 32 * 1024;  // groups the inner pass by staged LDS
@@ -577,8 +726,11 @@ FitPlan plan_fit(const ChainDesc* descs, int nchains, int32_t* tables) {
     grp[1][c] = accg[1];
     int64_t J0 = 1;
     for (int k = 1; k < d.N; ++k) J0 *= d.dims[k];
+    // as many blocks as the part holds two of (the same number of rows for
+    // each: no CU left with a single block's work), fewer for small tensors
     int64_t nb = (J0 + kFitRowsMin - 1) / kFitRowsMin;
     if (nb < 1) nb = 1;
+    if (nb > kFitBlocksMax) nb = kFitBlocksMax;
     if (nb > kFitParts) nb = kFitParts;
     // one inner pass stages at most 64 rank columns
     const size_t rt16 = std::min<size_t>(16 * (size_t)((d.R + 15) / 16), 64);
