@@ -208,7 +208,7 @@ __device__ __forceinline__ int fit_chain_of(const int32_t* start, int nchains, i
 // Inner pass over the ranks [r_off, r_off + 64) (up to four rank tiles);
 // R > 64 takes a second pass (r_off = 64) whose sums are added to the first's.
 template <typename T, bool INNER>
-__global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc* __restrict__ descs,
+__global__ void __launch_bounds__(kFitBlock) __attribute__((amdgpu_waves_per_eu(4))) fit_partial_kernel(const ChainDesc* __restrict__ descs,
                                                                 const int32_t* __restrict__ start,
                                                                 int nchains, int lds_floats,
                                                                 int r_off) {
@@ -242,6 +242,16 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rq = lane & 15, kg = lane >> 4;
   const CPD_GLOBAL float* A0 = gmem((const float*)dp->A[0]);
+  const CPD_GLOBAL char* X0 = gmem((const char*)dp->X[0]);
+  w4 va[U], vb[U];  // inner pass: chunk buffers, the first one carried across tiles
+  if (INNER && r0 + 16 * wave < r1) {
+    // the wave's first chunk is in flight while A^(1) is staged
+    const int64_t t0 = r0 + 16 * wave;
+    const int64_t jr = t0 + rq < J0 ? t0 + rq : J0 - 1;
+    const CPD_GLOBAL w4* xr = (const CPD_GLOBAL w4*)(X0 + jr * (int64_t)ld0 * sizeof(T));
+#pragma unroll
+    for (int u = 0; u < U; ++u) va[u] = xr[4 * u + kg];
+  }
   if (in_lds) {
     for (int e = tid; e < 16 * RT * P; e += kFitBlock) a0t[e] = 0.f;
     __syncthreads();
@@ -266,9 +276,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
   }
   const bool small_rows = J0 < ((int64_t)1 << 31);
   const int nit = (I0 + 63) / 64;
-  const CPD_GLOBAL char* X0 = gmem((const char*)dp->X[0]);
   double accd = 0.0;
-  w4 va[U], vb[U];  // inner pass: chunk buffers, the first one carried across tiles
   for (int64_t t0 = r0 + 16 * wave; t0 < r1; t0 += 16 * (kFitBlock / 64)) {
     const int64_t jr = t0 + rq < J0 ? t0 + rq : J0 - 1;  // rows past the end: any valid row
     const CPD_GLOBAL w4* xr = (const CPD_GLOBAL w4*)(X0 + jr * (int64_t)ld0 * sizeof(T));
@@ -345,9 +353,55 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
         }
       }
     };
-    if (t0 == r0 + 16 * wave) {
+    // The epilogue's factor entries, loaded now so that their round trips
+    // overlap the products.  Lane (kg, rq) holds y of rows jb..jb+3 (jb =
+    // t0 + 4 kg), column 16 rt + rq.  z_j = A^(2)(i_2) (x) w with w the
+    // product over the higher modes, shared by the four rows unless i_2
+    // wraps inside them (then the row takes the general path at the end);
+    // A^(2) rows and the entries of modes 3 and 4 are prefetched, higher
+    // modes (five-way and beyond) are loaded in the epilogue.
+    const int64_t jb = t0 + 4 * kg;
+    const int I1 = dp->dims[1];
+    int i1b;
+    int64_t hi;
+    if (small_rows) {
+      const uint32_t h = (uint32_t)jb / (uint32_t)I1;
+      i1b = (int)((uint32_t)jb - h * (uint32_t)I1);
+      hi = h;
+    } else {
+      hi = jb / I1;
+      i1b = (int)(jb - hi * I1);
+    }
+    int colc[4];  // the lane's rank columns, clamped into the row (zeros selected after)
 #pragma unroll
-      for (int u = 0; u < U; ++u) va[u] = xr[4 * u + kg];
+    for (int rt = 0; rt < 4; ++rt) {
+      const int col = r_off + 16 * rt + rq;
+      colc[rt] = col < R ? col : R - 1;
+    }
+    float wpre[2][4];
+    int64_t hrem = hi;
+#pragma unroll
+    for (int k2 = 0; k2 < 2; ++k2) {
+      const int k = 2 + k2;
+      if (k < N) {
+        const int Ik = dp->dims[k];
+        const int64_t nxt = small_rows ? (int64_t)((uint32_t)hrem / (uint32_t)Ik) : hrem / Ik;
+        const int ik = (int)(hrem - nxt * Ik);
+        hrem = nxt;
+        const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]) + (int64_t)ik * R;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) wpre[k2][rt] = Ak[colc[rt]];
+      }
+    }
+    float a1pre[4][4];
+    {
+      const CPD_GLOBAL float* A1 = gmem((const float*)dp->A[1]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i1 = i1b + q < I1 ? i1b + q : I1 - 1;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) a1pre[q][rt] = A1[(int64_t)i1 * R + colc[rt]];
+      }
     }
     // the first chunk of this wave's next tile is loaded during the last
     // chunk and the epilogue of this one
@@ -369,36 +423,26 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
       }
       if (it + 1 < nit) compute(vb, it + 1);
     }
-    // lane holds y(row 4 kg + q, column 16 rt + rq).  z_j = A^(2)(i_2) (x)
-    // w with w the product over the higher modes, shared by the four rows
-    // unless i_2 wraps inside them (then the row takes the general path).
     float part = 0.f;
-    const int64_t jb = t0 + 4 * kg;
-    const int I1 = dp->dims[1];
-    int i1b;
-    int64_t hi;
-    if (small_rows) {
-      const uint32_t h = (uint32_t)jb / (uint32_t)I1;
-      i1b = (int)((uint32_t)jb - h * (uint32_t)I1);
-      hi = h;
-    } else {
-      hi = jb / I1;
-      i1b = (int)(jb - hi * I1);
+    float w[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const int col = r_off + 16 * rt + rq;
+      float v = 1.f;
+      if (N > 2) v *= wpre[0][rt];
+      if (N > 3) v *= wpre[1][rt];
+      w[rt] = (rt < RT && col < R) ? v : 0.f;
     }
-    float w[4] = {1.f, 1.f, 1.f, 1.f};
     {
-      int64_t rem = hi;
-      for (int k = 2; k < N; ++k) {
+      int64_t rem = hrem;
+      for (int k = 4; k < N; ++k) {
         const int Ik = dp->dims[k];
         const int64_t nxt = small_rows ? (int64_t)((uint32_t)rem / (uint32_t)Ik) : rem / Ik;
         const int ik = (int)(rem - nxt * Ik);
         rem = nxt;
         const CPD_GLOBAL float* Ak = gmem((const float*)dp->A[k]) + (int64_t)ik * R;
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          const int col = r_off + 16 * rt + rq;
-          if (rt < RT) w[rt] *= col < R ? Ak[col] : 0.f;
-        }
+        for (int rt = 0; rt < 4; ++rt) w[rt] *= Ak[colc[rt]];
       }
     }
     const CPD_GLOBAL float* A1 = gmem((const float*)dp->A[1]);
@@ -410,10 +454,7 @@ __global__ void __launch_bounds__(kFitBlock) fit_partial_kernel(const ChainDesc*
         const int i1 = i1b + q;
         if (i1 < I1) {
 #pragma unroll
-          for (int rt = 0; rt < 4; ++rt) {
-            const int col = r_off + 16 * rt + rq;
-            z[rt] = (rt < RT && col < R) ? A1[(int64_t)i1 * R + col] * w[rt] : 0.f;
-          }
+          for (int rt = 0; rt < 4; ++rt) z[rt] = a1pre[q][rt] * w[rt];
         } else {
           // i_2 wrapped: the general multi-index of row j
           int64_t rem = j;
