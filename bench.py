@@ -160,8 +160,9 @@ def _oracle_batch_member(spec, budget):
 def oracle_beside(budget=25.0):
     """The FP64 oracle beside the other workloads, on bounded samples: the
     small 30^3 workload (its 2000 steps, one core), the 120^4 workload (a
-    few steps, one core) and the 64-tensor batch recipe (its first members,
-    one per worker process, each to fit 0.99 within the time budget)."""
+    few steps, one core), the 64-tensor batch recipe and the serving trace
+    (their first members / requests, one per worker process, each to fit
+    0.99 within the time budget)."""
     import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
 
@@ -204,6 +205,23 @@ def oracle_beside(budget=25.0):
                               f"each to fit 0.99 (explicit fit every 25 steps) within {budget:.0f} s",
                     "reached": reached, "wall_seconds": wall,
                     "steps": [r["steps"] for r in res]}
+    # the serving trace: its first requests, one per process, all submitted
+    # at once (the CPU pool is far behind the 50/s arrivals)
+    reqs = ci.request_trace(workers)
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers,
+                             mp_context=multiprocessing.get_context("spawn")) as ex:
+        res = list(ex.map(_oracle_serve_request, reqs, [budget] * len(reqs)))
+    wall = time.perf_counter() - t0
+    reached = sum(r["reached"] for r in res)
+    out["serve"] = {"value": reached / wall, "unit": "solves/s", "cores": workers,
+                    "kind": "oracle",
+                    "sample": f"first {len(reqs)} requests of the serving trace (host-built "
+                              "tensors of the same recipe), one per process, each to fit 0.99 "
+                              f"(explicit fit every 25 steps) within {budget:.0f} s",
+                    "reached": reached, "wall_seconds": wall,
+                    "steps": [r["steps"] for r in res],
+                    "dims": [q["dims"] for q in reqs]}
     return out
 
 
@@ -451,6 +469,33 @@ def batch_bench(count=64, seq=True):
 
 
 SERVE_ETA = 1.0
+
+
+def _oracle_serve_request(spec, budget):
+    """One request of the serving trace solved by the FP64 oracle (in a worker
+    process): the request's shape, rank, seeds and B, its tensor from the
+    host recipe (the server's is formed on the device, whose noise draws
+    differ), AdaGrad with the explicit-reconstruction fit every 25 steps,
+    until fit 0.99, 5000 steps or the time budget."""
+    import cpd_inputs as ci
+    import oracle as O
+    t0 = time.perf_counter()
+    prob = ci.make_problem(spec["dims"], spec["R"], data_seed=spec["data_seed"],
+                           init_seed=spec["init_seed"], snr_db=spec["snr_db"], dtype="bf16")
+    orc = O.Oracle(prob["X"], prob["A0"], B=spec["B"], sampler="euclidean", rule="adagrad",
+                   eta=SERVE_ETA, seed=spec["seed"], stream_id=spec["stream_id"])
+    t1 = time.perf_counter()
+    steps, fit = 0, -1.0
+    while steps < 5000 and time.perf_counter() - t0 < budget:
+        for _ in range(25):
+            orc.step()
+        steps += 25
+        fit = orc.fit()
+        if fit >= 0.99:
+            break
+    return {"steps": steps, "fit": fit, "reached": fit >= 0.99,
+            "solve_seconds": time.perf_counter() - t1,
+            "setup_seconds": t1 - t0}
 
 
 def serve_bench(n_requests=200, rate=50.0, saturate=False):
