@@ -30,8 +30,8 @@ constexpr int kFibrePad = 4 * kChunkSteps;  // sampled fibres padded (zero weigh
 constexpr int kFibreBufs = 2;           // register buffers of fibre chunks in the contraction
 constexpr double kRankTol = 1e-12;      // Cholesky pivot^2 <= tol * diagonal => rank deficient
 constexpr size_t kLdsBudget = 160 * 1024;  // LDS per workgroup on gfx950
-constexpr int kFitRowsMin = 64;         // rows of copy 0 per fit block, at least
-constexpr int kFitBlocksMax = 512;      // fit blocks per decomposition: two per CU of a 256-CU part
+constexpr int kFitRowsMin = 256;        // rows of copy 0 per fit block, at least
+constexpr int kFitBlocksMax = 512;      // fit blocks of one decomposition, at most (past 131 072 rows)
 constexpr size_t kFitLdsMax = 64 * 1024;  // A^(1) staged in LDS by the fit kernel up to this
 
 // Row stride (floats) of the transposed A^(1) the fit kernel stages in LDS:

@@ -760,27 +760,43 @@ FitPlan plan_fit(const ChainDesc* descs, int nchains, int32_t* tables) {
   int32_t* all = tables;
   int32_t* grp[2] = {tables + (nchains + 1), tables + 2 * (nchains + 1)};
   int32_t acc = 0, accg[2] = {0, 0};
+  // A^(1) staging need and LDS group (light / heavy: one inner launch each)
+  // of a chain; one inner pass stages at most 64 rank columns
+  auto need_of = [&](const ChainDesc& d) {
+    const size_t rt16 = std::min<size_t>(16 * (size_t)((d.R + 15) / 16), 64);
+    const size_t need32 = sizeof(float) * rt16 * fit_a0_stride(d.dims[0]);
+    const size_t need16 = 2 * sizeof(uint16_t) * rt16 * fit_a0_stride16(d.dims[0]);
+    size_t need = (d.dtype == CPD_BF16 && need16 <= kFitLdsMax) ? need16 : need32;
+    if (need > kFitLdsMax) need = 0;  // A^(1) read from global memory
+    return need;
+  };
+  auto rows_of = [&](const ChainDesc& d) {
+    int64_t J0 = 1;
+    for (int k = 1; k < d.N; ++k) J0 *= d.dims[k];
+    return J0;
+  };
+  // rows per block of a chain: at least kFitRowsMin (each block stages
+  // A^(1), and the members of a full batch or server round share the GPU, so
+  // more, shorter blocks only add staging), more for tensors that would
+  // otherwise take over kFitBlocksMax blocks (two per CU).  A function of
+  // the chain alone: a batch member and a single handle on the same tensor
+  // split their rows the same way, so their fits agree to the bit.
+  auto rpb_of = [&](int64_t J0) {
+    const int64_t r = (J0 + kFitBlocksMax - 1) / kFitBlocksMax;
+    return r < kFitRowsMin ? (int64_t)kFitRowsMin : r;
+  };
   for (int c = 0; c < nchains; ++c) {
     const ChainDesc& d = descs[c];
     all[c] = acc;
     grp[0][c] = accg[0];
     grp[1][c] = accg[1];
-    int64_t J0 = 1;
-    for (int k = 1; k < d.N; ++k) J0 *= d.dims[k];
-    // as many blocks as the part holds two of (the same number of rows for
-    // each: no CU left with a single block's work), fewer for small tensors
-    int64_t nb = (J0 + kFitRowsMin - 1) / kFitRowsMin;
-    if (nb < 1) nb = 1;
-    if (nb > kFitBlocksMax) nb = kFitBlocksMax;
-    if (nb > kFitParts) nb = kFitParts;
-    // one inner pass stages at most 64 rank columns
-    const size_t rt16 = std::min<size_t>(16 * (size_t)((d.R + 15) / 16), 64);
     if (d.R > 64) fp.passes = 2;
-    const size_t need32 = sizeof(float) * rt16 * fit_a0_stride(d.dims[0]);
-    const size_t need16 = 2 * sizeof(uint16_t) * rt16 * fit_a0_stride16(d.dims[0]);
-    size_t need = (d.dtype == CPD_BF16 && need16 <= kFitLdsMax) ? need16 : need32;
-    if (need > kFitLdsMax) need = 0;  // A^(1) read from global memory
+    const size_t need = need_of(d);
     const int g = need <= kFitLightLds ? 0 : 1;
+    const int64_t J0 = rows_of(d), rpb = rpb_of(J0);
+    int64_t nb = (J0 + rpb - 1) / rpb;
+    if (nb < 1) nb = 1;
+    if (nb > kFitParts) nb = kFitParts;
     acc += (int32_t)nb;
     accg[g] += (int32_t)nb;
     if (need > fp.lds[g]) fp.lds[g] = need;
