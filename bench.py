@@ -31,14 +31,14 @@ ETA = 5.0
 # scaled by a 256 MiB device copy (FETCH x2.000, WRITE x1.000), 5000-step dispatch.  Valid only
 # for the kernel sources it was taken on: reported as null once any hash differs.
 MEASURED_TRAFFIC = {
-    "bytes_per_step": (2.0 * 63625.375 + 1574.78125) * 1024 / 5000,
+    "bytes_per_step": (262144 / 131088.25 * 63265.8125 + 1945.625) * 1024 / 5000,
     "sources": {
         "paper_2103_04081_amd/csrc/step_kernel.hip":
             "836006f5c15d226f994dc6eda5e19166cd9b8ba157fb0c3f7073b661f344820b",
         "paper_2103_04081_amd/csrc/step_common.hpp":
             "76aa2143d8b948f8b1dd56199d62bbce7d11d82870f233957898644ee0276b2d",
         "paper_2103_04081_amd/csrc/cpd_internal.hpp":
-            "fced12af7d94d43adc3d803933a7cff94dfaae77ff8a20b7ea606b748e0303b3",
+            "3b3cb343dd3761dd30721b34db95d3ff3373c49eaf4d875c49722fd6c1fe2087",
     },
     "profile": "profiles/chain_kernel_300cube_R10_B256_f32.md",
 }
