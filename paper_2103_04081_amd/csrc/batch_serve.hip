@@ -3,8 +3,10 @@
 // Members are ordered by rank-tile class (RT = ceil(R / 16)); each class is
 // one launch of the persistent step kernel with one workgroup per member,
 // and the classes run concurrently on two streams.  A round (fit_every
-// steps of every member, then one fit launch over all members) is captured
-// once in a HIP graph and replayed.
+// steps of every member of a class, then the fit check of that class, on
+// the class's stream) is captured once in a HIP graph and replayed: the
+// fit of a class that finishes its steps early streams its tensors while
+// the other class still steps.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -30,6 +32,8 @@ std::map<std::tuple<int, int, int, int>, int> g_tuned;
 struct Group {
   int rt, first, count;
   size_t lds;
+  FitPlan fit{{0, 0}, {0, 0}, 1};  // the class's own fit launches
+  int32_t* d_fitmap = nullptr;     // their block tables (descriptors first .. first+count)
 };
 
 }  // namespace
@@ -80,7 +84,10 @@ cpd_status plan_batch(const cpd_problem* ps, const cpd_options* os, int count,
   L->states = off;
   off = align_up(off + sizeof(ChainState) * count);
   L->fitmap = off;
-  off = align_up(off + sizeof(int32_t) * fit_table_len(count));
+  // all members' tables, then one set per rank-tile class (at most
+  // kMaxRankTiles classes, each at most count members)
+  off = align_up(off + sizeof(int32_t) * (fit_table_len(count) + fit_table_len(count) +
+                                          3 * (kMaxRankTiles - 1)));
   L->base.resize(count);
   for (int i = 0; i < count; ++i) {
     std::string why;
@@ -274,19 +281,44 @@ hipError_t launch_fit_all(cpd_batch* b, hipStream_t stream) {
   return launch_fit(b->d_descs, b->d_fitmap, b->count, b->fit, b->dtype, true, stream);
 }
 
-cpd_status build_graph(cpd_batch* b) {
-  hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+// One round: every class steps fit_every steps and then checks the fit of
+// its own members, on the class's stream (the first class on main, the
+// others on the side stream, forked from and joined back into main).
+hipError_t launch_round(cpd_batch* b, hipStream_t main) {
   StepArgs a{};
   a.op = OP_STEP;
   a.nsteps = b->fit_every;
-  hipError_t e1 = launch_groups(b, a, b->cap);
-  hipError_t e2 = e1 == hipSuccess ? launch_fit_all(b, b->cap) : e1;
+  const bool fork = b->groups.size() > 1;
+  hipError_t e = hipSuccess;
+  if (fork) {
+    e = hipEventRecord(b->fork, main);
+    if (e != hipSuccess) return e;
+    e = hipStreamWaitEvent(b->side, b->fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    const Group& g = b->groups[gi];
+    hipStream_t s = gi == 0 ? main : b->side;
+    e = launch_chain_kernel(b->d_descs + g.first, g.count, g.rt, g.lds, a, s);
+    if (e != hipSuccess) return e;
+    e = launch_fit(b->d_descs + g.first, g.d_fitmap, g.count, g.fit, b->dtype, true, s);
+    if (e != hipSuccess) return e;
+  }
+  if (!fork) return hipSuccess;
+  e = hipEventRecord(b->join, b->side);
+  if (e != hipSuccess) return e;
+  return hipStreamWaitEvent(main, b->join, 0);
+}
+
+cpd_status build_graph(cpd_batch* b) {
+  hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  hipError_t e1 = launch_round(b, b->cap);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(b->cap, &g);
-  if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
+  if (e1 != hipSuccess || e != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
-    return hip_fail(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e), "graph capture");
+    return hip_fail(e1 != hipSuccess ? e1 : e, "graph capture");
   }
   hipGraphExec_t x = nullptr;
   e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
@@ -411,6 +443,10 @@ cpd_status cpd_batch_create(const cpd_problem* ps, const cpd_options* os, int32_
       g.count++;
       g.lds = std::max(g.lds, plans[i].lds);
     }
+    if (b->groups.size() > (size_t)kMaxRankTiles) {
+      set_error("more rank-tile classes than the persistent step has");
+      return fail(CPD_E_INVALID);
+    }
     e = hipMemsetAsync(b->ws, 0, L.states + sizeof(ChainState) * count, b->stream);
     if (e != hipSuccess) return fail(hip_fail(e, "hipMemsetAsync"));
     for (int i = 0; i < count; ++i) {
@@ -439,12 +475,23 @@ cpd_status cpd_batch_create(const cpd_problem* ps, const cpd_options* os, int32_
       s = restart_members(b, A0);
       if (s != CPD_OK) return fail(s);
     }
-    std::vector<int32_t> fitmap(fit_table_len(count));
-    b->fit = plan_fit(b->descs.data(), count, fitmap.data());
+    // all members' tables, then each class's own (the same block split of
+    // each member, a function of its tensor alone, over the class's
+    // descriptors); one copy
+    size_t ntab = fit_table_len(count);
+    for (const Group& g : b->groups) ntab += fit_table_len(g.count);
+    std::vector<int32_t> fitmap(ntab);
     b->d_fitmap = (int32_t*)(b->ws + L.fitmap);
+    b->fit = plan_fit(b->descs.data(), count, fitmap.data());
+    size_t at = fit_table_len(count);
+    for (Group& g : b->groups) {
+      g.fit = plan_fit(b->descs.data() + g.first, g.count, fitmap.data() + at);
+      g.d_fitmap = b->d_fitmap + at;
+      at += fit_table_len(g.count);
+    }
     e = hipMemcpyAsync(b->d_fitmap, fitmap.data(), sizeof(int32_t) * fitmap.size(),
                        hipMemcpyHostToDevice, b->stream);
-    if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpyAsync(fit table)"));
+    if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpyAsync(fit tables)"));
     e = launch_fit(b->d_descs, b->d_fitmap, count, b->fit, b->dtype, false, b->stream);
     if (e != hipSuccess) return fail(hip_fail(e, "norm kernels"));
     s = read_states(b);

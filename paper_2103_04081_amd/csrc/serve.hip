@@ -2,8 +2,9 @@
 //
 // Two host threads per server:
 //   the round thread: launch round_steps steps of every running request (one
-//     launch of the persistent step kernel per rank-tile class) and one fit
-//     check of all of them on the step stream; wait; hand out the requests
+//     launch of the persistent step kernel per rank-tile class, the classes
+//     concurrently on two streams) and one fit check of all of them on the
+//     step stream; wait; hand out the requests
 //     that stopped; install the requests admitted meanwhile; repeat;
 //   the admission thread: take waiting requests in order as slots and arena
 //     space free up and initialise them on the admission stream (staging,
@@ -116,6 +117,8 @@ struct cpd_server {
   char* arena = nullptr;
   size_t arena_bytes = 0, heap_off = 0;
   hipStream_t step = nullptr, admit = nullptr;
+  hipStream_t side = nullptr;  // rank-tile classes after the first, concurrent with it
+  hipEvent_t fork = nullptr, join = nullptr;
   // device header
   ChainDesc* d_class[kClasses] = {};  // per rank-tile class, one entry per slot
   ChainDesc* d_fit[2] = {};           // per storage type, one entry per slot
@@ -304,10 +307,26 @@ hipError_t launch_round(cpd_server* s) {
   StepArgs a{};
   a.op = OP_STEP;
   a.nsteps = s->cfg.round_steps;
-  for (int c = 0; c < kClasses; ++c) {
+  // the first populated class steps on the step stream, the others one
+  // after the other on the side stream, forked from and joined back into
+  // the step stream (classes are independent of each other)
+  int populated = 0;
+  for (int c = 0; c < kClasses; ++c) populated += s->class_count[c] ? 1 : 0;
+  hipError_t e = hipSuccess;
+  if (populated > 1) {
+    e = hipEventRecord(s->fork, s->step);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->side, s->fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  for (int c = 0, q = 0; c < kClasses; ++c) {
     if (!s->class_count[c]) continue;
-    hipError_t e = launch_chain_kernel(s->d_class[c], s->cfg.max_slots, c + 1, s->class_lds[c], a,
-                                       s->step);
+    e = launch_chain_kernel(s->d_class[c], s->cfg.max_slots, c + 1, s->class_lds[c], a,
+                            q++ == 0 ? s->step : s->side);
+    if (e != hipSuccess) return e;
+  }
+  if (populated > 1) {
+    e = hipEventRecord(s->join, s->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->step, s->join, 0);
     if (e != hipSuccess) return e;
   }
   for (int d = 0; d < 2; ++d) {
@@ -478,6 +497,9 @@ cpd_status cpd_server_create(const cpd_server_config* cfg, void* arena, size_t a
       cpd_status r = hip_fail(e, what);
       if (s->step) (void)hipStreamDestroy(s->step);
       if (s->admit) (void)hipStreamDestroy(s->admit);
+      if (s->side) (void)hipStreamDestroy(s->side);
+      if (s->fork) (void)hipEventDestroy(s->fork);
+      if (s->join) (void)hipEventDestroy(s->join);
       delete s;
       return r;
     };
@@ -491,6 +513,11 @@ cpd_status cpd_server_create(const cpd_server_config* cfg, void* arena, size_t a
     if (e != hipSuccess) return fail(e, "hipStreamCreate");
     e = hipStreamCreateWithFlags(&s->admit, hipStreamNonBlocking);
     if (e != hipSuccess) return fail(e, "hipStreamCreate");
+    e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(e, "hipStreamCreate");
+    e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(e, "hipEventCreate");
     for (int c = 0; c < kClasses; ++c) {
       s->d_class[c] = (ChainDesc*)(s->arena + H.cls[c]);
       s->h_class[c].assign(cfg->max_slots, ChainDesc{});
@@ -617,9 +644,13 @@ cpd_status cpd_server_destroy(cpd_server* s) {
   if (s->admitter.joinable()) s->admitter.join();
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->step);
+  (void)hipStreamSynchronize(s->side);
   (void)hipStreamSynchronize(s->admit);
   (void)hipStreamDestroy(s->step);
+  (void)hipStreamDestroy(s->side);
   (void)hipStreamDestroy(s->admit);
+  (void)hipEventDestroy(s->fork);
+  (void)hipEventDestroy(s->join);
   delete s;
   return CPD_OK;
 }
