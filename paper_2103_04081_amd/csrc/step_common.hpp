@@ -11,6 +11,66 @@ namespace cpdmi {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+// One chunk (U K-steps of 4 fibres) of the contraction of BF16-stored
+// fibres, on v_mfma_f32_16x16x32_bf16 in K blocks of 32 fibres.  wa[u4][rt]
+// holds the lane's WH values of K-steps 4 u4 .. 4 u4 + 3 (rank tile rt),
+// x[u][v] the lane's fibre values (exact BF16 in FP32) of K-step u, as the
+// v_mfma_f32_16x16x4f32 form takes them.  Slot i of lane group g of the
+// BF16 instruction is the fibre of K-step 4 (2p + i/4) + i%4 of the same
+// lane, so both operands come from those registers: the fibre values as
+// they are, WH cut by truncation into three BF16 terms whose sum is the
+// FP32 value exactly.  Every product is then exact in FP32 and the sums
+// are FP32, at 3 x 16 instead of 8 x 32 matrix-core cycles per 32 fibres.
+// hi and lo terms go to acc, mid terms to acc2.
+template <int U, int RT, int VW>
+__device__ __forceinline__ void mfma_wh_x_bf16(const f4 (&wa)[U / 4][RT], const float (&x)[U][VW],
+                                               f4 (&acc)[RT][VW], f4 (&acc2)[RT][VW]) {
+  static_assert(U % 8 == 0, "K blocks of 32 fibres");
+#pragma unroll
+  for (int p = 0; p < U / 8; ++p) {
+    u4v bx[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        bx[v][q] = (__float_as_uint(x[8 * p + 2 * q][v]) >> 16) |
+                   (__float_as_uint(x[8 * p + 2 * q + 1][v]) & 0xFFFF0000u);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      u4v ah, am, al;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t hb[2], mb[2], lb[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int i = 2 * q + e;
+          const float w = wa[2 * p + i / 4][rt][i % 4];
+          hb[e] = __float_as_uint(w) & 0xFFFF0000u;
+          const float r1 = w - __uint_as_float(hb[e]);
+          mb[e] = __float_as_uint(r1) & 0xFFFF0000u;
+          lb[e] = __float_as_uint(r1 - __uint_as_float(mb[e]));
+        }
+        ah[q] = (hb[0] >> 16) | hb[1];
+        am[q] = (mb[0] >> 16) | mb[1];
+        al[q] = (lb[0] >> 16) | (lb[1] & 0xFFFF0000u);
+      }
+      const bf8v a_h = __builtin_bit_cast(bf8v, ah);
+      const bf8v a_m = __builtin_bit_cast(bf8v, am);
+      const bf8v a_l = __builtin_bit_cast(bf8v, al);
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        const bf8v b = __builtin_bit_cast(bf8v, bx[v]);
+        acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, b, acc[rt][v], 0, 0, 0);
+        acc2[rt][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_m, b, acc2[rt][v], 0, 0, 0);
+        acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, b, acc[rt][v], 0, 0, 0);
+      }
+    }
+  }
+}
+
 extern __shared__ __align__(16) unsigned char cpd_smem[];
 
 // Offsets of the LDS regions of one workgroup.  Pointers are always formed

@@ -26,9 +26,6 @@
 
 namespace cpdmi {
 
-typedef uint32_t u4v __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
-
 // A^(n) into mbuf (row i at mbuf[i * ms]) for the contraction epilogue, in
 // two halves so the loads can be in flight while the draws are searched:
 // prefetch_issue loads the first kPrefetch * kBlock entries into registers,
@@ -267,53 +264,7 @@ __device__ __forceinline__ bool contract_update(const ChainDesc* dp, const Smem&
       for (int rt = 0; rt < RT; ++rt)
         wa[u4][rt] = *(const f4*)(wht + ((kq0 + u4) * RT + rt) * 256 + lane * 4);
     if constexpr (BF16 && U % 8 == 0) {
-      // K blocks of 32 fibres on v_mfma_f32_16x16x32_bf16.  Slot i of lane
-      // group g is the fibre that K-step 4 (2p + i/4) + i%4 of the FP32 form
-      // gives the same lane, so the stored BF16 values are the B operand as
-      // loaded, and the A operand is the lane's own WH values split by
-      // truncation into three BF16 terms, WH = hi + mid + lo exactly.  The
-      // products are exact in FP32 and accumulate in FP32 as in the FP32
-      // form, at 3 x 16 instead of 8 x 32 matrix-core cycles per 32 fibres.
-#pragma unroll
-      for (int p = 0; p < U / 8; ++p) {
-        u4v bx[VW];
-#pragma unroll
-        for (int v = 0; v < VW; ++v)
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            bx[v][q] = (__float_as_uint(x[8 * p + 2 * q][v]) >> 16) |
-                       (__float_as_uint(x[8 * p + 2 * q + 1][v]) & 0xFFFF0000u);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          u4v ah, am, al;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            uint32_t hb[2], mb[2], lb[2];
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-              const int i = 2 * q + e;
-              const float w = wa[2 * p + i / 4][rt][i % 4];
-              hb[e] = __float_as_uint(w) & 0xFFFF0000u;
-              const float r1 = w - __uint_as_float(hb[e]);
-              mb[e] = __float_as_uint(r1) & 0xFFFF0000u;
-              lb[e] = __float_as_uint(r1 - __uint_as_float(mb[e]));
-            }
-            ah[q] = (hb[0] >> 16) | hb[1];
-            am[q] = (mb[0] >> 16) | mb[1];
-            al[q] = (lb[0] >> 16) | (lb[1] & 0xFFFF0000u);
-          }
-          const bf8v a_h = __builtin_bit_cast(bf8v, ah);
-          const bf8v a_m = __builtin_bit_cast(bf8v, am);
-          const bf8v a_l = __builtin_bit_cast(bf8v, al);
-#pragma unroll
-          for (int v = 0; v < VW; ++v) {
-            const bf8v b = __builtin_bit_cast(bf8v, bx[v]);
-            acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, b, acc[rt][v], 0, 0, 0);
-            acc2[rt][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_m, b, acc2[rt][v], 0, 0, 0);
-            acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, b, acc[rt][v], 0, 0, 0);
-          }
-        }
-      }
+      mfma_wh_x_bf16<U, RT, VW>(wa, x, acc, acc2);
     } else {
 #pragma unroll
       for (int u4 = 0; u4 < U / 4; ++u4) {

@@ -342,19 +342,23 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
         wa[u4][rt] = *(const f4*)(whtc + ((kq0 + u4) * RT + rt) * 256 + lane * 4);
+    if constexpr (BF16 && U % 8 == 0) {
+      mfma_wh_x_bf16<U, RT, VW>(wa, x, acc, acc2);
+    } else {
 #pragma unroll
-    for (int u4 = 0; u4 < U / 4; ++u4)
+      for (int u4 = 0; u4 < U / 4; ++u4)
 #pragma unroll
-      for (int j = 0; j < 4; j += 2)
+        for (int j = 0; j < 4; j += 2)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+          for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-          for (int v = 0; v < VW; ++v) {
-            acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[u4][rt][j], x[4 * u4 + j][v],
-                                                              acc[rt][v], 0, 0, 0);
-            acc2[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                wa[u4][rt][j + 1], x[4 * u4 + j + 1][v], acc2[rt][v], 0, 0, 0);
-          }
+            for (int v = 0; v < VW; ++v) {
+              acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[u4][rt][j], x[4 * u4 + j][v],
+                                                                acc[rt][v], 0, 0, 0);
+              acc2[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                  wa[u4][rt][j + 1], x[4 * u4 + j + 1][v], acc2[rt][v], 0, 0, 0);
+            }
+    }
     if (ci == c1 - 1) epilogue(tg + it * tgn, pA);
   };
   const int total = nitems * nckw;
