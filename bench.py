@@ -31,12 +31,12 @@ ETA = 5.0
 # scaled by a 256 MiB device copy (FETCH x2.000, WRITE x1.000), 5000-step dispatch.  Valid only
 # for the kernel sources it was taken on: reported as null once any hash differs.
 MEASURED_TRAFFIC = {
-    "bytes_per_step": (262144 / 131088.25 * 63265.8125 + 1945.625) * 1024 / 5000,
+    "bytes_per_step": (262144 / 131087.6875 * 63625.25 + 1574.78125) * 1024 / 5000,
     "sources": {
         "paper_2103_04081_amd/csrc/step_kernel.hip":
-            "836006f5c15d226f994dc6eda5e19166cd9b8ba157fb0c3f7073b661f344820b",
+            "22a49e85e29ed80ebcb870d321dee071f8dd2c8ed1302571a11c786d536af934",
         "paper_2103_04081_amd/csrc/step_common.hpp":
-            "76aa2143d8b948f8b1dd56199d62bbce7d11d82870f233957898644ee0276b2d",
+            "95a7a1aded1513aa486317098cc77e499934468c221344ce4ee6a40716074baf",
         "paper_2103_04081_amd/csrc/cpd_internal.hpp":
             "3b3cb343dd3761dd30721b34db95d3ff3373c49eaf4d875c49722fd6c1fe2087",
     },
@@ -454,7 +454,7 @@ def batch_bench(count=64, seq=True):
                     f"storage, SNR 30 dB; Euclidean sampler, AdaGrad eta={BATCH_ETA}; fit check "
                     "every 25 steps; each run to fit 0.99 or 5000 steps",
         "solves_per_s": count / run_s, "seconds": run_s, "reached": reached,
-        "remaining": left, "rounds": rounds,
+        "remaining": left, "rounds": rounds, "ms_per_round": run_s / max(rounds, 1) * 1e3,
         "steps_to_fit_p50": float(np.percentile(steps, 50)),
         "steps_to_fit_p99": float(np.percentile(steps, 99)),
         "device_seconds_to_fit_p50": float(np.percentile(secs, 50)),
