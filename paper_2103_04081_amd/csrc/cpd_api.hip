@@ -343,6 +343,7 @@ static WideArgs wide_args(cpd_handle* h, int op) {
   WideArgs a{};
   a.op = op;
   a.fb = h->plan.wide_fb;
+  a.tsplit = wide_tsplit(h->plan.wide_blocks);
   a.part = (float*)(h->ws + h->plan.wide_part);
   a.info = (WideInfo*)(h->ws + h->plan.wide_info);
   return a;

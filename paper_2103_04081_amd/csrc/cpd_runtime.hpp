@@ -33,7 +33,7 @@ hipError_t launch_fit(const ChainDesc* d_descs, const int32_t* d_tables, int nch
                       const FitPlan& fp, int dtype, bool inner, hipStream_t stream);
 
 // Grid-wide step (wide_step.hip).  Gather: nblocks slices of a.fb fibres,
-// wide_kparts parts of -G^T each; update: the parts of every entry of mode n summed
+// a.tsplit blocks per slice, wide_kparts parts of -G^T per slice; update: the parts of every entry of mode n summed
 // and applied (launched over max_rows * R entries); refresh: the CDF of mode `mode` (-1: every
 // one of the nmodes modes, one block each; -2: the mode in info).
 hipError_t launch_wide_gather(const ChainDesc* d_desc, int rt, int dtype, int nblocks,

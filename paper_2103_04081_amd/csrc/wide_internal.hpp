@@ -39,6 +39,19 @@ __host__ __device__ inline int wide_kparts(int nst, int nck) {
   return kp;
 }
 
+// Gather blocks per slice.  With few slices the row tiles of the updated
+// mode are dealt over several blocks of the same slice (each repeats the
+// slice's draws, WH rows and Gs), so that a small mini-batch at a large
+// rank is not one CU's work; a tile's arithmetic is the same whichever
+// block runs it, and the blocks of a slice write disjoint rows of the
+// slice's parts.
+constexpr int kWideTileSplitMax = 16;
+inline int wide_tsplit(int nslices) {
+  int g = 1;
+  while (g < kWideTileSplitMax && nslices * g * 2 <= 64) g *= 2;
+  return g;
+}
+
 // Mode and step of the step in flight, written by the gather kernel for the
 // update and refresh kernels that follow it on the stream.
 struct WideInfo {
@@ -51,7 +64,8 @@ struct WideArgs {
   int32_t op;           // OP_STEP, OP_SAMPLE or OP_REPLAY
   int32_t replay_mode;  // OP_REPLAY: the mode
   int32_t force_mode1;  // OP_STEP timing runs: 1 + the mode every step uses; 0 = drawn
-  int32_t fb;           // fibres per block (a multiple of kFibrePad)
+  int32_t fb;           // fibres per slice (a multiple of kFibrePad)
+  int32_t tsplit;       // gather blocks per slice (wide_tsplit)
   uint64_t sample_t;
   const int32_t* replay_idx;
   int32_t* out_idx;

@@ -34,7 +34,9 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
   const int fl = lane >> 4, cl = lane & 15;
   const int N = dp->N, R = dp->R, B = dp->B, nm1 = N - 1;
   const int FB = a.fb;
-  const int f0 = blockIdx.x * FB;
+  // block tb of slice `slice` (a.tsplit blocks per slice)
+  const int slice = blockIdx.x / a.tsplit, tb = blockIdx.x - slice * a.tsplit;
+  const int f0 = slice * FB;
   const int nf = B - f0 < FB ? B - f0 : FB;
   const GatherPlan P = gather_plan(N, dp->dims, RT, FB);
   Smem S;
@@ -169,7 +171,7 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
       S.wf()[f] = (float)(1.0 / ((double)B * p));
       S.rinv()[f] = (float)((double)B * p);
       S.rowb()[ro] = (uint32_t)(j * ldn * esz);
-      if (a.op == OP_SAMPLE) {
+      if (a.op == OP_SAMPLE && tb == 0) {
         gmem(a.out_p)[f0 + f] = p;
         for (int q = 0; q < nm1; ++q)
           gmem(a.out_idx)[(int64_t)(f0 + f) * nm1 + q] = S.idx()[f * nm1 + q];
@@ -232,24 +234,26 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
   const int SW = 16 * VW;
   const int nst = (In + SW - 1) / SW;
   const int nck = S.bpad / (4 * U);
-  // wave w owns tiles tg, tg + 8/kp, ... of its tile group and walks each
-  // over its part of the slice's fibres (long runs of loads in flight per
-  // wave measured faster than walking the tiles chunk by chunk).  Every
-  // block splits its chunks as a full slice would, so the part count is the
-  // same for all blocks; waves of a short last block may get no chunk.
+  // wave w owns tiles tgi, tgi + tgs, ... of its tile group (tile group
+  // tgi = tb * 8/kp + w % (8/kp) of the slice's tsplit * 8/kp groups) and
+  // walks each over its part of the slice's fibres (long runs of loads in
+  // flight per wave measured faster than walking the tiles chunk by chunk).
+  // Every block splits its chunks as a full slice would, so the part count
+  // is the same for all slices; waves of a short last slice may get no chunk.
   const int nck_full = FB / (4 * U);
   const int kp = wide_kparts(nst, nck_full);
   const int tgn = kGatherWaves / kp;
-  const int tg = wave % tgn, kpart = wave / tgn;
+  const int kpart = wave / tgn;
+  const int tg = tb * tgn + wave % tgn, tgs = a.tsplit * tgn;
   const int c0 = kpart * nck_full / kp;
   const int c1 = min((kpart + 1) * nck_full / kp, nck);
   const int nckw = c1 > c0 ? c1 - c0 : 0;
-  const int nitems = tg < nst ? (nst - 1 - tg) / tgn + 1 : 0;
+  const int nitems = tg < nst ? (nst - 1 - tg) / tgs + 1 : 0;
   const float* __restrict__ whtc = S.wht();
   const uint32_t* __restrict__ rowb = S.rowb();
   const CPD_GLOBAL char* __restrict__ Xb = gmem((const char*)dp->X[n]);
   const CPD_GLOBAL float* An = gmem(dp->A[n]);
-  CPD_GLOBAL float* part = gmem(a.part) + ((int64_t)blockIdx.x * kp + kpart) * R * In;
+  CPD_GLOBAL float* part = gmem(a.part) + ((int64_t)slice * kp + kpart) * R * In;
   const int rp16 = S.rp16;
 
   f4 acc[RT][VW], acc2[RT][VW];
@@ -259,7 +263,7 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
   float pbuf[kGatherBufs][4 * RT][VW];
   auto load = [&](float (&x)[U][VW], float (&pA)[4 * RT][VW], int c) {
     const int it = c / nckw;
-    const int stl = tg + it * tgn;
+    const int stl = tg + it * tgs;
     const int ci = c0 + (c - it * nckw);
     const int kq0 = ci * (U / 4);  // first group of four K-steps
     const uint32_t colb = (uint32_t)((stl * SW + cl * VW) * (BF16 ? 2 : 4));
@@ -359,13 +363,13 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
                   wa[u4][rt][j + 1], x[4 * u4 + j + 1][v], acc2[rt][v], 0, 0, 0);
             }
     }
-    if (ci == c1 - 1) epilogue(tg + it * tgn, pA);
+    if (ci == c1 - 1) epilogue(tg + it * tgs, pA);
   };
   const int total = nitems * nckw;
   if (nitems > 0 && nckw == 0) {
     // a short last block: this part of every tile of the wave is zero
     for (int it = 0; it < nitems; ++it) {
-      const int col0 = (tg + it * tgn) * SW;
+      const int col0 = (tg + it * tgs) * SW;
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -547,7 +551,8 @@ static hipError_t gather_rt(const ChainDesc* d, int nblocks, size_t lds, const W
                             hipStream_t s) {
   hipError_t e = gather_attr<RT, BF16>();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((wide_gather_kernel<RT, BF16>), dim3(nblocks), dim3(kGatherThreads), lds, s, d, a);
+  hipLaunchKernelGGL((wide_gather_kernel<RT, BF16>), dim3(nblocks * a.tsplit), dim3(kGatherThreads),
+                     lds, s, d, a);
   return hipGetLastError();
 }
 
