@@ -466,6 +466,42 @@ __global__ void __launch_bounds__(64 * kUpdWaves) wide_update_kernel(
   if (blockIdx.x == 0 && threadIdx.x == 0) st->t = t + 1;
 }
 
+// The same update when every entry has at most kGroups parts (few slices):
+// one thread per entry, the parts added in the order and with the zero
+// terms of wide_update_kernel's group sums, so the result is the same bits.
+constexpr int kUpdFewThreads = 256;
+__global__ void __launch_bounds__(kUpdFewThreads) wide_update_few_kernel(
+    const ChainDesc* __restrict__ dp, const float* __restrict__ part, int nblocks, int fb,
+    const WideInfo* __restrict__ info) {
+  constexpr int kGroups = 4 * kUpdWaves;
+  ChainState* st = dp->state;
+  const int n = info->n;
+  const int64_t t = info->t;
+  if (st->status != 0) return;
+  const int In = dp->dims[n], R = dp->R, E = In * R;
+  const int vw = dp->dtype == CPD_BF16 ? 2 : 1;
+  const int nparts =
+      nblocks * wide_kparts((In + 16 * vw - 1) / (16 * vw), fb / (4 * chunk_steps(vw, dp->RT)));
+  const int e = blockIdx.x * kUpdFewThreads + (int)threadIdx.x;
+  if (e < E) {
+    const int64_t ai = (int64_t)(e % In) * R + e / In;
+    CPD_GLOBAL float* An = gmem(dp->A[n]);
+    CPD_GLOBAL float* Sn = gmem(dp->S[n]);
+    const UpdateParams up = update_params(dp, (uint64_t)t);
+    const float a_old = An[ai];
+    float sacc = up.ada ? Sn[ai] : 0.f;
+    const CPD_GLOBAL float* pp = gmem(part) + e;
+    float m = 0.f + pp[0];
+    for (int q = 1; q < nparts; ++q) m = m + (0.f + pp[(int64_t)q * E]);
+    if (nparts < kGroups) m = m + 0.f;
+    const float an = update_entry(up, a_old, -m, sacc);
+    if (up.ada) Sn[ai] = sacc;
+    An[ai] = an;
+    if (!isfinite(an)) st->status = CPD_E_DIVERGED;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->t = t + 1;
+}
+
 // CDF of one mode (mode >= 0), of every mode (-1, one block per mode) or of
 // the mode of the step in flight (-2, after its update).
 template <int RT>
@@ -575,6 +611,13 @@ hipError_t launch_wide_gather(const ChainDesc* d_desc, int rt, int dtype, int nb
 
 hipError_t launch_wide_update(const ChainDesc* d_desc, const float* part, int nblocks, int fb,
                               const WideInfo* info, int max_entries, hipStream_t stream) {
+  if (nblocks * kWideMaxParts <= 4 * kUpdWaves) {
+    // at most 4 * kUpdWaves parts per entry whatever the mode
+    const int grid = (max_entries + kUpdFewThreads - 1) / kUpdFewThreads;
+    hipLaunchKernelGGL(wide_update_few_kernel, dim3(grid), dim3(kUpdFewThreads), 0, stream,
+                       d_desc, part, nblocks, fb, info);
+    return hipGetLastError();
+  }
   const int grid = (max_entries + kUpdEntries - 1) / kUpdEntries;
   hipLaunchKernelGGL(wide_update_kernel, dim3(grid), dim3(64 * kUpdWaves), 0, stream, d_desc,
                      part, nblocks, fb, info);
