@@ -256,10 +256,34 @@ __device__ __forceinline__ int leverage_one_tile(const ChainDesc* dp, const Smem
   return err;
 }
 
+// Euclidean weight of row i held in global memory: the sum over r (in
+// order) of A(i, r)^2 in FP64, each square exact, as the LDS form below
+// computes it, with the entries loaded eight at a time.
+__device__ __forceinline__ double row_sq_global(const float* mb, int i, int ms, int R) {
+  double acc = 0.0;
+  int r = 0;
+  for (; r + 8 <= R; r += 8) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = mb[i * ms + r + j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double a = (double)v[j];
+      acc = acc + a * a;
+    }
+  }
+  for (; r < R; ++r) {
+    const double a = (double)mb[i * ms + r];
+    acc = acc + a * a;  // a*a is exact in FP64 for an FP32 a
+  }
+  return acc;
+}
+
 // ---------------------------------------------------------------------------
-// CDF of mode n from its factor rows in LDS (row i at mb[i * ms]).
+// CDF of mode n from its factor rows (row i at mb[i * ms]): in LDS, or in
+// global memory for GROWS (Euclidean and uniform sampling only).
 // ---------------------------------------------------------------------------
-template <int RT>
+template <int RT, bool GROWS = false>
 __device__ __forceinline__ int refresh_cdf(const ChainDesc* dp, const Smem& S, int n,
                                            const float* mb, int ms) {
   const int R = dp->R, In = dp->dims[n];
@@ -380,9 +404,13 @@ __device__ __forceinline__ int refresh_cdf(const ChainDesc* dp, const Smem& S, i
     double wi = 0.0;
     if (i < In) {
       if (dp->sampler == CPD_SAMPLER_EUCLIDEAN) {
-        for (int r = 0; r < R; ++r) {
-          const double a = (double)mb[i * ms + r];
-          wi = wi + a * a;  // a*a is exact in FP64 for an FP32 a
+        if constexpr (GROWS) {
+          wi = row_sq_global(mb, i, ms, R);
+        } else {
+          for (int r = 0; r < R; ++r) {
+            const double a = (double)mb[i * ms + r];
+            wi = wi + a * a;  // a*a is exact in FP64 for an FP32 a
+          }
         }
       } else if (dp->sampler == CPD_SAMPLER_UNIFORM) {
         wi = 1.0;
@@ -422,9 +450,13 @@ __device__ __forceinline__ int refresh_cdf(const ChainDesc* dp, const Smem& S, i
     for (int i = threadIdx.x; i < In; i += kBlock) {
       double acc = 0.0;
       if (dp->sampler == CPD_SAMPLER_EUCLIDEAN) {
-        for (int r = 0; r < R; ++r) {
-          const double a = (double)mb[i * ms + r];
-          acc = acc + a * a;
+        if constexpr (GROWS) {
+          acc = row_sq_global(mb, i, ms, R);
+        } else {
+          for (int r = 0; r < R; ++r) {
+            const double a = (double)mb[i * ms + r];
+            acc = acc + a * a;
+          }
         }
       } else {
         acc = 1.0;

@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(kBlock) wide_refresh_kernel(const ChainDesc* _
       err = refresh_cdf<RT>(dp, S, n, S.mbuf(), S.ms);
     } else {
       // rows too large for LDS: the squared row norms from global memory
-      err = refresh_cdf<RT>(dp, S, n, dp->A[n], R);
+      err = refresh_cdf<RT, true>(dp, S, n, dp->A[n], R);
     }
     __syncthreads();
   }
