@@ -100,6 +100,8 @@ def parse():
                     help="only time the fit check (300^3 FP32 and 120^4 BF16, 40 fits each)")
     ap.add_argument("--grid-only", action="store_true",
                     help="run only the large-batch grid sweep (profiling)")
+    ap.add_argument("--scenes-only", action="store_true",
+                    help="run only the scene-shaped workloads (profiling)")
     ap.add_argument("--grid-b", default="4096,16384,65536,131072,262144",
                     help="mini-batch sizes of the grid sweep")
     ap.add_argument("--grid-steps", type=int, default=100)
@@ -267,6 +269,9 @@ def main():
         print(json.dumps({"serve": serve_bench(args.serve_requests),
                           "serve_saturated": serve_bench(args.serve_requests, saturate=True)}),
               flush=True)
+        return
+    if args.scenes_only:
+        print(json.dumps({"scenes": scenes()}), flush=True)
         return
     w = ci.workload(2)
     dims, R, B = w["dims"], w["R"], w["B"]
