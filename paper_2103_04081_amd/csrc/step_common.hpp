@@ -509,8 +509,9 @@ __device__ __forceinline__ int refresh_cdf(const ChainDesc* dp, const Smem& S, i
 //   A operand (16 x 4): lane l holds WH[f0 + l/16][rt*16 + l%16]
 //   B operand (4 x 16): lane l holds H[f0 + l/16][ct*16 + l%16]
 //   D (16 x 16): lane l, element q holds row 4*(l/16)+q, column l%16
+// Gs rows are rp16 + GPAD floats apart in LDS.
 // ---------------------------------------------------------------------------
-template <int RT, int NT = kBlock>
+template <int RT, int NT = kBlock, int GPAD = 0>
 __device__ __forceinline__ void compute_gs(const Smem& S) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = uniform_int(threadIdx.x >> 6);
@@ -539,7 +540,8 @@ __device__ __forceinline__ void compute_gs(const Smem& S) {
     if constexpr (kparts == 1) {
       // one part per tile: straight to Gs
 #pragma unroll
-      for (int e = 0; e < 4; ++e) S.gs()[(rt * 16 + 4 * fl + e) * S.rp16 + ct * 16 + cl] = g[e];
+      for (int e = 0; e < 4; ++e)
+        S.gs()[(rt * 16 + 4 * fl + e) * (S.rp16 + GPAD) + ct * 16 + cl] = g[e];
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) gsp[it * 256 + (4 * fl + e) * 16 + cl] = g[e];
@@ -554,7 +556,7 @@ __device__ __forceinline__ void compute_gs(const Smem& S) {
     float acc = 0.f;
     for (int kp = 0; kp < kparts; ++kp)
       acc += gsp[(kp * T2 + tile) * 256 + (r & 15) * 16 + (s2 & 15)];
-    S.gs()[e] = acc;
+    S.gs()[r * (rp16 + GPAD) + s2] = acc;
   }
   __syncthreads();
 }

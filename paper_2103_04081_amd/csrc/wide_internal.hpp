@@ -15,6 +15,10 @@ constexpr int kWideFibresMax = 512;
 constexpr int kGatherThreads = 512;  // threads of a gather block
 constexpr int kGatherWaves = kGatherThreads / 64;
 constexpr int kGatherBufs = 2;  // register buffers of fibre chunks per wave
+// Gs rows are 16 RT + kGsPad floats apart in the gather kernel's LDS: the
+// epilogue's lanes (16 rows x 4 rank columns per read) then hit 64
+// distinct banks instead of 4 at RT = 8.
+constexpr int kGsPad = 4;
 
 // Fibres per block of the gather kernel for mini-batch B: about 256 blocks
 // while the slices stay within [128, 512] fibres (measured on 300-element
@@ -101,7 +105,7 @@ __host__ __device__ inline GatherPlan gather_plan(int N, const int32_t* dims, in
   p.rinv = take(sizeof(float) * fb);
   p.rowoff = take(sizeof(uint32_t) * fb);
   p.wht = take(sizeof(float) * (size_t)fb * rp16);
-  p.gs = take(sizeof(float) * (size_t)rp16 * rp16);
+  p.gs = take(sizeof(float) * (size_t)rp16 * (rp16 + kGsPad));
   // Gs partials only when fewer tiles than waves split the fibres (with at
   // least as many tiles as waves every tile is written straight to gs)
   p.gsp = take(t2 >= kGatherWaves ? 0 : sizeof(float) * 256 * (size_t)kGatherWaves);

@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
       const int s = 4 * kk + fl;
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        const float g = -S.gs()[(rt * 16 + cl) * rp16 + s];
+        const float g = -S.gs()[(rt * 16 + cl) * (rp16 + kGsPad) + s];
 #pragma unroll
         for (int v = 0; v < VW; ++v)
           acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, pA[kk][v], acc[rt][v], 0, 0, 0);
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
 #pragma unroll
   for (int j = 0; j < kGatherBufs - 1; ++j)
     if (j < total) load(xbuf[j], pbuf[j], j);
-  compute_gs<RT, kGatherThreads>(S);
+  compute_gs<RT, kGatherThreads, kGsPad>(S);
   for (int c = 0; c < total; c += kGatherBufs) {
 #pragma unroll
     for (int j = 0; j < kGatherBufs; ++j) {
