@@ -523,6 +523,43 @@ __device__ __forceinline__ void compute_gs(const Smem& S) {
   const float* wht = S.wht();
   const float* rinv = S.rinv();
   float* gsp = S.gsp();
+  if constexpr (T2 >= 2 * NW && NW % RT == 0) {
+    // several whole tiles per wave, all in the wave's column tile
+    // ct = wave % RT: the H operand is formed once per K group and up to
+    // four tiles accumulate side by side (independent matrix-core chains),
+    // each in the same order as one tile alone
+    constexpr int M = T2 / NW;
+    constexpr int MB = M < 4 ? M : 4;
+    const int ct = wave % RT;
+    for (int m0 = 0; m0 < M; m0 += MB) {
+      f4 g[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) g[mb] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int q = 0; q < nq; ++q) {
+        const f4 h4 = *(const f4*)(wht + (q * RT + ct) * 256 + lane * 4);
+        float b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = h4[j] * rinv[(4 * q + j) * 4 + fl];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const int rt = (wave + NW * (m0 + mb)) / RT;
+          const f4 a4 = *(const f4*)(wht + (q * RT + rt) * 256 + lane * 4);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            g[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[j], b[j], g[mb], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int rt = (wave + NW * (m0 + mb)) / RT;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          S.gs()[(rt * 16 + 4 * fl + e) * (S.rp16 + GPAD) + ct * 16 + cl] = g[mb][e];
+      }
+    }
+    __syncthreads();
+    return;
+  }
   for (int it = wave; it < items; it += NW) {
     const int tile = it % T2, kp = it / T2;
     const int rt = tile / RT, ct = tile % RT;
