@@ -2,7 +2,9 @@
 // step is the same as the persistent kernel's (paper Section 3, Algorithms
 // 3-5; the same Philox words, integer CDFs, draws and step rules), spread
 // over the whole GPU in three launches:
-//   wide_gather_kernel   every block takes a slice of the B sampled fibres:
+//   wide_gather_kernel   every block takes a slice of the B sampled fibres
+//                        (with few slices, several blocks share a slice
+//                        and split its row tiles):
 //                        the Philox blocks of its draws, inverse-CDF search
 //                        over the CDFs in LDS, p_f, w_f and the WH rows, its
 //                        part of Gs = (WH)^T H, then its part of
@@ -234,8 +236,8 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
   const int SW = 16 * VW;
   const int nst = (In + SW - 1) / SW;
   const int nck = S.bpad / (4 * U);
-  // wave w owns tiles tgi, tgi + tgs, ... of its tile group (tile group
-  // tgi = tb * 8/kp + w % (8/kp) of the slice's tsplit * 8/kp groups) and
+  // wave w owns tiles tg, tg + tgs, ... of its tile group (tile group
+  // tg = tb * 8/kp + w % (8/kp) of the slice's tgs = tsplit * 8/kp) and
   // walks each over its part of the slice's fibres (long runs of loads in
   // flight per wave measured faster than walking the tiles chunk by chunk).
   // Every block splits its chunks as a full slice would, so the part count
