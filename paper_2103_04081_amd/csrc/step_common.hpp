@@ -258,16 +258,17 @@ __device__ __forceinline__ int leverage_one_tile(const ChainDesc* dp, const Smem
 
 // Euclidean weight of row i held in global memory: the sum over r (in
 // order) of A(i, r)^2 in FP64, each square exact, as the LDS form below
-// computes it, with the entries loaded eight at a time.
+// computes it, with the entries loaded sixteen at a time.
 __device__ __forceinline__ double row_sq_global(const float* mb, int i, int ms, int R) {
+  constexpr int kW = 16;
   double acc = 0.0;
   int r = 0;
-  for (; r + 8 <= R; r += 8) {
-    float v[8];
+  for (; r + kW <= R; r += kW) {
+    float v[kW];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = mb[i * ms + r + j];
+    for (int j = 0; j < kW; ++j) v[j] = mb[i * ms + r + j];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < kW; ++j) {
       const double a = (double)v[j];
       acc = acc + a * a;
     }
