@@ -43,16 +43,18 @@ __host__ __device__ inline int wide_kparts(int nst, int nck) {
   return kp;
 }
 
-// Gather blocks per slice.  With few slices the row tiles of the updated
-// mode are dealt over several blocks of the same slice (each repeats the
-// slice's draws, WH rows and Gs), so that a small mini-batch at a large
-// rank is not one CU's work; a tile's arithmetic is the same whichever
-// block runs it, and the blocks of a slice write disjoint rows of the
-// slice's parts.
+// Gather blocks per slice.  With fewer slices than CUs the row tiles of
+// the updated mode are dealt over several blocks of the same slice (each
+// repeats the slice's draws, WH rows and Gs), up to one block per CU in all,
+// so that a small mini-batch is not a few CUs' work; a tile's arithmetic is
+// the same whichever block runs it, and the blocks of a slice write
+// disjoint rows of the slice's parts.  (Measured on the 300^3 step: 64
+// blocks in all left B = 8192 at 18.5 us, 256 give 15.7 us, 512 give 20.2.)
 constexpr int kWideTileSplitMax = 16;
+constexpr int kWideSplitBlocks = 256;
 inline int wide_tsplit(int nslices) {
   int g = 1;
-  while (g < kWideTileSplitMax && nslices * g * 2 <= 64) g *= 2;
+  while (g < kWideTileSplitMax && nslices * g * 2 <= kWideSplitBlocks) g *= 2;
   return g;
 }
 
