@@ -15,9 +15,8 @@ constexpr int kWideFibresMax = 512;
 constexpr int kGatherThreads = 512;  // threads of a gather block
 constexpr int kGatherWaves = kGatherThreads / 64;
 constexpr int kGatherBufs = 2;  // register buffers of fibre chunks per wave
-// Gs rows are 16 RT + kGsPad floats apart in the gather kernel's LDS: the
-// epilogue's lanes (16 rows x 4 rank columns per read) then hit 64
-// distinct banks instead of 4 at RT = 8.
+// Gs rows are 16 RT + kGsPad floats apart in the gather kernel's LDS (rows
+// 16 RT floats apart put the 16 rows an epilogue read spans in one bank).
 constexpr int kGsPad = 4;
 
 // Fibres per block of the gather kernel for mini-batch B: about 256 blocks

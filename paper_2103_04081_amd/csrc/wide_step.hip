@@ -229,9 +229,11 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
   // ---- this slice's -G^T, per 16-column tile of the I_n x R output ---------
   //   A operand: lane l holds WH[f0 + l/16][rt*16 + l%16]           (LDS)
   //   B operand: lane l holds X_s[f0 + l/16][col0 + (l%16)*VW + v]   (HBM)
-  // then K = rank with A = -Gs[rt*16 + l%16][s] and B = A^(n)[col][s].
+  // then K = rank with A = -Gs[rt*16 + l%16][s] and B = A^(n)[col][s],
+  // s = 4 kk + l/16 at step kk (kk + 4 RT (l/16) from four rank tiles).
   constexpr int VW = BF16 ? 2 : 1;
   constexpr int U = chunk_steps(VW, RT);  // K-steps per chunk
+  constexpr bool kGsVec = RT >= 4;        // the epilogue's Gs entries in 16-byte reads
   const int In = dp->dims[n];
   const int SW = 16 * VW;
   const int nst = (In + SW - 1) / SW;
@@ -292,7 +294,7 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
       const int col0 = stl * SW;
 #pragma unroll
       for (int kk = 0; kk < 4 * RT; ++kk) {
-        const int s = 4 * kk + fl;
+        const int s = kGsVec ? kk + 4 * RT * fl : 4 * kk + fl;  // K slot fl of step kk
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
           const int i = col0 + cl * VW + v;
@@ -307,16 +309,42 @@ __global__ void __launch_bounds__(kGatherThreads) wide_gather_kernel(const Chain
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int v = 0; v < VW; ++v) acc[rt][v] += acc2[rt][v];
+    if constexpr (!kGsVec) {
 #pragma unroll
-    for (int kk = 0; kk < 4 * RT; ++kk) {
-      const int s = 4 * kk + fl;
+      for (int kk = 0; kk < 4 * RT; ++kk) {
+        const int s = 4 * kk + fl;
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        const float g = -S.gs()[(rt * 16 + cl) * (rp16 + kGsPad) + s];
+        for (int rt = 0; rt < RT; ++rt) {
+          const float g = -S.gs()[(rt * 16 + cl) * (rp16 + kGsPad) + s];
 #pragma unroll
-        for (int v = 0; v < VW; ++v)
-          acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, pA[kk][v], acc[rt][v], 0, 0, 0);
+          for (int v = 0; v < VW; ++v)
+            acc[rt][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, pA[kk][v], acc[rt][v], 0, 0, 0);
+        }
       }
+    } else {
+      // four or more rank tiles: step kk, slot fl is rank s = kk + 4 RT fl,
+      // so a lane's Gs entries of four consecutive steps are one 16-byte LDS
+      // read (rank tiles four at a time: at most four reads in registers)
+#pragma unroll
+      for (int kk4 = 0; kk4 < RT; ++kk4)
+#pragma unroll
+        for (int r0 = 0; r0 < RT; r0 += 4) {
+          f4 g4[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (r0 + r < RT)
+              g4[r] = *(const f4*)(S.gs() + ((r0 + r) * 16 + cl) * (rp16 + kGsPad) +
+                                   4 * RT * fl + 4 * kk4);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (r0 + r < RT)
+#pragma unroll
+                for (int v = 0; v < VW; ++v)
+                  acc[r0 + r][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                      -g4[r][j], pA[4 * kk4 + j][v], acc[r0 + r][v], 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
