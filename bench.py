@@ -319,6 +319,8 @@ def main():
     extra = {}
     if not args.no_fit:
         extra["time_to_fit"] = time_to_fit(make, target=0.99, every=25, max_steps=40000)
+        extra["time_to_fit"]["euclidean_device_rounds"] = time_to_fit_rounds(
+            X32, w, B, target=0.99, every=25, max_steps=40000)
         progress("time_to_fit")
     if not args.no_batch:
         extra["batch"] = batch_bench(args.batch_count, seq=not args.no_seq)
@@ -887,6 +889,27 @@ def time_to_fit(make, target, every, max_steps):
     res["check_every"] = every
     res["target"] = target
     return res
+
+
+def time_to_fit_rounds(X32, w, B, target, every, max_steps):
+    """The same Euclidean run as a batch of one: rounds of `every` steps and a
+    fit check replayed from a HIP graph, the stop decided on the device (no
+    host round trip per check).  Same draws and arithmetic as the single
+    handle, so the same steps to fit."""
+    import torch
+
+    import paper_2103_04081_amd as P
+    b = P.Batch([dict(X=X32, A0=w["A0"], B=B, sampler="euclidean", rule="adagrad", eta=ETA,
+                      storage="f32", fit_every=every, fit_target=target, max_steps=max_steps,
+                      seed=w["seed"])], tune=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(max_rounds=max_steps // every + 1)
+    el = time.perf_counter() - t0
+    inf = b.info(0)
+    b.close()
+    return {"steps": inf["t_done"], "seconds": el, "device_seconds": inf["seconds_done"],
+            "fit": inf["fit"], "reached": inf["fit"] >= target}
 
 
 if __name__ == "__main__":
