@@ -439,6 +439,7 @@ __global__ void __launch_bounds__(64 * kUpdWaves) wide_update_kernel(
     const ChainDesc* __restrict__ dp, const float* __restrict__ part, int nblocks, int fb,
     const WideInfo* __restrict__ info) {
   constexpr int kGroups = 4 * kUpdWaves;
+  static_assert(kUpdEntries == 16, "one entry per lane of a 16-lane group");
   __shared__ float red[kGroups][kUpdEntries + 1];
   __shared__ int sh_stop, sh_n;
   __shared__ int64_t sh_t;
