@@ -252,7 +252,7 @@ def main():
         args.no_fit = args.no_batch = args.no_rescale = args.no_grid = True
         args.no_variance = args.no_serve = args.no_oracle_extra = True
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: measures a single GPU (no multi-GPU path); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
